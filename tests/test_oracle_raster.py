@@ -1,0 +1,346 @@
+"""Pins of the oracle's projection and compositing (Sec. "Differentiable 3D
+Gaussian Splatting"; Sec. "Image Gradient Based Upscaling", 3DGS image
+gradients; Suppl. "3DGS Gradient Computation - Forward pass").
+
+Each test checks the oracle against something other than itself: finite
+differences of the composited colour, the closed form of a single isotropic
+Gaussian, a SymPy derivation for two overlapping Gaussians, the product-rule
+sum written with explicit transmittance products, an independent EWA
+construction (SciPy rotations and a finite-difference Jacobian), the
+early-termination error bound, the pixel mapping between resolutions, and a
+brute-force check of the alpha_min support box.
+"""
+import numpy as np
+import pytest
+import sympy as sp
+from scipy.spatial.transform import Rotation
+
+from paper_2503_14171_amd import scenes
+
+SMOOTH = dict(alpha_min=1e-300, alpha_max=1.0, t_min=1e-300)
+
+
+def _small_scene(n=1500, seed=11, deg=0, size=48):
+    sc = scenes.make_scene("uniform", n, seed, deg)
+    cam = scenes.make_camera(size, size)
+    return sc, cam
+
+
+def _proj(pts, conic, opac, rgb):
+    n = len(opac)
+    return dict(valid=np.ones(n, bool), mean2d=np.asarray(pts, float), conic=np.asarray(conic, float),
+                opacity=np.asarray(opac, float), rgb=np.asarray(rgb, float), depth=np.arange(n, dtype=float) + 1)
+
+
+# ---------------------------------------------------------------------------
+# P3: single isotropic Gaussian on the optical axis
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.2, 0.5, 0.9)])
+def test_single_isotropic_gaussian_closed_form(oracle, bg):
+    s_log, sigma, z = np.float32(-1.6), np.float32(0.8), 3.0
+    sc = dict(means=np.zeros((1, 3), np.float32), log_scales=np.full((1, 3), s_log, np.float32),
+              quats=np.array([[1, 0, 0, 0]], np.float32), opacity=np.array([sigma], np.float32),
+              sh=np.array([[[0.7, -0.3, 1.1]]], np.float32))
+    cam = scenes.make_camera(40, 30)
+    cfg = scenes.render_config(0, bg=bg)
+    pr = oracle.project(sc, cam, cfg)
+    order = oracle.depth_order(pr)
+    rng = np.random.default_rng(0)
+    px = rng.uniform(7, 32, 300)
+    py = rng.uniform(2, 27, 300)
+    r = oracle.composite(pr, order, cfg, px, py)["out"]
+    f = float(np.float32(cam["fx"]))
+    v = (f * np.exp(float(s_log)) / z) ** 2 + float(np.float32(0.3))
+    dx = px - float(np.float32(cam["cx"]))
+    dy = py - float(np.float32(cam["cy"]))
+    alpha = float(sigma) * np.exp(-(dx * dx + dy * dy) / (2 * v))
+    keep = alpha >= float(np.float32(cfg["alpha_min"]))
+    c = 0.5 + np.array([0.7, -0.3, 1.1], np.float32).astype(float) / (2 * np.sqrt(np.pi))
+    bgv = np.array(bg, np.float32).astype(float)
+    a = np.where(keep, alpha, 0.0)
+    I = a[:, None] * c + (1 - a)[:, None] * bgv
+    Ix = (c - bgv) * (-a * dx / v)[:, None]
+    Iy = (c - bgv) * (-a * dy / v)[:, None]
+    Ixy = (c - bgv) * (a * dx * dy / v ** 2)[:, None]
+    assert keep.sum() > 50 and (~keep).sum() > 50
+    np.testing.assert_allclose(r, np.concatenate([I, Ix, Iy, Ixy], 1), atol=1e-12, rtol=1e-12)
+
+
+def test_alpha_clamp_zeroes_derivatives(oracle):
+    """alpha above alpha_max is clamped to alpha_max and its screen derivatives vanish."""
+    pr = _proj([[10.0, 10.0]], [[0.5, 0.1, 0.4]], [1.0], [[0.3, 0.6, 0.9]])
+    cfg = scenes.render_config(0)
+    r = oracle.composite(pr, np.array([0]), cfg, [10.01, 10.0], [10.0, 10.02])["out"]
+    np.testing.assert_allclose(r[:, :3], np.tile(0.99 * np.array([0.3, 0.6, 0.9]), (2, 1)), atol=1e-7)
+    np.testing.assert_array_equal(r[:, 3:], 0.0)
+
+
+# ---------------------------------------------------------------------------
+# P4: two overlapping Gaussians, derived symbolically
+# ---------------------------------------------------------------------------
+def test_two_gaussians_sympy(oracle):
+    x, y = sp.symbols("x y", real=True)
+    mus = [(5.2, 6.1), (6.0, 5.5)]
+    conics = [(0.6, 0.15, 0.4), (0.3, -0.1, 0.5)]
+    sig = [0.7, 0.85]
+    cols = [(0.9, 0.2, 0.4), (0.1, 0.8, 0.5)]
+    bg = (0.0625, 0.125, 0.25)  # FP32-exact: render settings are FP32 numbers
+    al = []
+    for (mx, my), (a, b, c), s in zip(mus, conics, sig):
+        dx, dy = x - mx, y - my
+        al.append(s * sp.exp(-sp.Rational(1, 2) * (a * dx ** 2 + 2 * b * dx * dy + c * dy ** 2)))
+    exprs = []
+    for ch in range(3):
+        I = cols[0][ch] * al[0] + cols[1][ch] * al[1] * (1 - al[0]) + (1 - al[0]) * (1 - al[1]) * bg[ch]
+        exprs.append([I, sp.diff(I, x), sp.diff(I, y), sp.diff(I, x, y)])
+    fn = sp.lambdify((x, y), exprs, "numpy")
+    pr = _proj(mus, conics, sig, cols)
+    cfg = scenes.render_config(0, bg=bg, **SMOOTH)
+    rng = np.random.default_rng(1)
+    px, py = rng.uniform(2, 9, 100), rng.uniform(2, 9, 100)
+    r = oracle.composite(pr, np.array([0, 1]), cfg, px, py)["out"]
+    for k in range(100):
+        e = np.array(fn(px[k], py[k]), float)  # [3 ch, 4 quantities]
+        np.testing.assert_allclose(r[k].reshape(4, 3), e.T, atol=1e-12, rtol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# P1: analytical derivatives vs central finite differences of the image
+# ---------------------------------------------------------------------------
+def _fd(oracle, pr, order, cfg, px, py, h1=1e-5, h2=1e-4, **kw):
+    f = lambda dx, dy: oracle.composite(pr, order, cfg, px + dx, py + dy, **kw)["out"][:, :3]
+    Ix = (f(h1, 0) - f(-h1, 0)) / (2 * h1)
+    Iy = (f(0, h1) - f(0, -h1)) / (2 * h1)
+    Ixy = (f(h2, h2) - f(h2, -h2) - f(-h2, h2) + f(-h2, -h2)) / (4 * h2 * h2)
+    return Ix, Iy, Ixy
+
+
+def test_derivatives_match_finite_differences_smooth(oracle):
+    sc, cam = _small_scene()
+    cfg = scenes.render_config(0, **SMOOTH)
+    pr = oracle.project(sc, cam, cfg)
+    order = oracle.depth_order(pr)
+    rng = np.random.default_rng(2)
+    px, py = rng.uniform(0, 47, 200), rng.uniform(0, 47, 200)
+    r = oracle.composite(pr, order, cfg, px, py)["out"]
+    Ix, Iy, Ixy = _fd(oracle, pr, order, cfg, px, py)
+    scale = 1 + np.abs(r[:, 3:12]).max()
+    assert np.abs(r[:, 3:12]).max() > 0.1
+    np.testing.assert_allclose(r[:, 3:6], Ix, atol=1e-6 * scale)
+    np.testing.assert_allclose(r[:, 6:9], Iy, atol=1e-6 * scale)
+    np.testing.assert_allclose(r[:, 9:12], Ixy, atol=1e-5 * scale)
+
+
+def test_derivatives_match_finite_differences_thresholds(oracle):
+    """With alpha_min / alpha_max / t_min active, at points whose decisions are
+    far from any tie the derivatives are those of the fixed fragment set."""
+    sc, cam = _small_scene(seed=12)
+    cfg = scenes.render_config(0)
+    pr = oracle.project(sc, cam, cfg)
+    order = oracle.depth_order(pr)
+    rng = np.random.default_rng(3)
+    px, py = rng.uniform(0, 47, 600), rng.uniform(0, 47, 600)
+    res = oracle.composite(pr, order, cfg, px, py, tie_alpha=5e-3, tie_t=5e-2)
+    ok = res["n_amb"] == 0
+    assert ok.sum() > 300
+    r = res["out"][ok]
+    Ix, Iy, Ixy = _fd(oracle, pr, order, cfg, px[ok], py[ok])
+    scale = 1 + np.abs(r[:, 3:12]).max()
+    np.testing.assert_allclose(r[:, 3:6], Ix, atol=1e-6 * scale)
+    np.testing.assert_allclose(r[:, 6:9], Iy, atol=1e-6 * scale)
+    np.testing.assert_allclose(r[:, 9:12], Ixy, atol=1e-5 * scale)
+
+
+# ---------------------------------------------------------------------------
+# P2: recurrences == explicit product-rule sum over transmittance products
+# ---------------------------------------------------------------------------
+def test_recurrence_equals_product_rule_sum(oracle):
+    sc, cam = _small_scene(n=800, seed=13)
+    bg = np.array([0.125, 0.25, 0.375])
+    cfg = scenes.render_config(0, bg=tuple(bg), **SMOOTH)
+    pr = oracle.project(sc, cam, cfg)
+    order = oracle.depth_order(pr)
+    rng = np.random.default_rng(4)
+    px, py = rng.uniform(0, 47, 60), rng.uniform(0, 47, 60)
+    r = oracle.composite(pr, order, cfg, px, py)["out"]
+    m = pr["mean2d"][order]
+    a, b, c = pr["conic"][order].T
+    sig = pr["opacity"][order]
+    col = pr["rgb"][order]
+    for k in range(60):
+        dx, dy = px[k] - m[:, 0], py[k] - m[:, 1]
+        g = -0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+        gx, gy = -(a * dx + b * dy), -(b * dx + c * dy)
+        al = sig * np.exp(g)
+        ax, ay, axy = al * gx, al * gy, al * (gx * gy - b)
+        # T_i = prod_{j<i} (1 - alpha_j); S = sum_{j<i} alpha_j,x / (1 - alpha_j), ...
+        T = np.concatenate([[1.0], np.cumprod(1 - al)[:-1]])
+        Sx = np.concatenate([[0.0], np.cumsum(ax / (1 - al))[:-1]])
+        Sy = np.concatenate([[0.0], np.cumsum(ay / (1 - al))[:-1]])
+        Sxy = np.concatenate([[0.0], np.cumsum((axy * (1 - al) + ax * ay) / (1 - al) ** 2)[:-1]])
+        Tx, Ty = -T * Sx, -T * Sy
+        Txy = T * (Sx * Sy - Sxy)
+        Tend = np.prod(1 - al)
+        Tend_x = -Tend * np.sum(ax / (1 - al))
+        Tend_y = -Tend * np.sum(ay / (1 - al))
+        Tend_xy = Tend * (np.sum(ax / (1 - al)) * np.sum(ay / (1 - al)) -
+                          np.sum((axy * (1 - al) + ax * ay) / (1 - al) ** 2))
+        I = (T * al) @ col + Tend * bg
+        Ix = (Tx * al + T * ax) @ col + Tend_x * bg
+        Iy = (Ty * al + T * ay) @ col + Tend_y * bg
+        Ixy = (Txy * al + Tx * ay + Ty * ax + T * axy) @ col + Tend_xy * bg
+        np.testing.assert_allclose(r[k], np.concatenate([I, Ix, Iy, Ixy]), atol=1e-12, rtol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# P9: early termination bound
+# ---------------------------------------------------------------------------
+def test_termination_error_bound(oracle):
+    sc, cam = _small_scene(n=4000, seed=14)
+    sc["opacity"][:] = np.float32(0.95)  # dense, opaque: most pixels terminate
+    cfg = scenes.render_config(0)
+    pr = oracle.project(sc, cam, cfg)
+    order = oracle.depth_order(pr)
+    yy, xx = np.meshgrid(np.arange(48.0), np.arange(48.0), indexing="ij")
+    full = oracle.composite(pr, order, cfg, xx.reshape(-1), yy.reshape(-1))
+    notrm = oracle.composite(pr, order, dict(cfg, t_min=1e-300), xx.reshape(-1), yy.reshape(-1))
+    stopped = full["n_blend"] < notrm["n_blend"]
+    assert stopped.sum() > 100
+    cmax = pr["rgb"][pr["valid"]].max()
+    err = np.abs(full["out"][:, :3] - notrm["out"][:, :3]).max()
+    assert err <= 1e-4 * cmax
+
+
+# ---------------------------------------------------------------------------
+# P5: EWA projection vs an independent construction
+# ---------------------------------------------------------------------------
+def test_projection_matches_independent_ewa(oracle):
+    sc = scenes.make_scene("uniform", 400, 15, 0)
+    sc["means"] *= np.float32(2.6)  # some leave the frustum (J clamp), some pass the near plane
+    cam = scenes.orbit_camera(64, 40, 30.0, 10.0)
+    cfg = scenes.render_config(0)
+    pr = oracle.project(sc, cam, cfg)
+    V = np.asarray(cam["view"], np.float64)
+    W, t = V[:, :3], V[:, 3]
+    fx, fy = float(cam["fx"]), float(cam["fy"])
+    cx, cy = float(cam["cx"]), float(cam["cy"])
+    mu = sc["means"].astype(np.float64)
+    tc = mu @ W.T + t
+    np.testing.assert_allclose(pr["depth"], tc[:, 2], atol=1e-13)
+    v = pr["valid"]
+    assert v.sum() > 200 and (~v).sum() > 0
+    np.testing.assert_array_equal(v, tc[:, 2] > float(cam["near_plane"]))
+    pi = lambda p: np.array([fx * p[0] / p[2] + cx, fy * p[1] / p[2] + cy])
+    limx, limy = 1.3 * 32 / fx, 1.3 * 20 / fy
+    clamped = 0
+    for i in np.nonzero(v)[0]:
+        np.testing.assert_allclose(pr["mean2d"][i], pi(tc[i]), atol=1e-10)
+        q = sc["quats"][i].astype(np.float64)
+        R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        s = np.exp(sc["log_scales"][i].astype(np.float64))
+        Sig = R @ np.diag(s * s) @ R.T
+        # Jacobian of the perspective map by central differences, at the mean
+        # with its direction clamped to 1.3x the half field of view
+        z = tc[i, 2]
+        p = np.array([np.clip(tc[i, 0] / z, -limx, limx) * z, np.clip(tc[i, 1] / z, -limy, limy) * z, z])
+        clamped += not np.allclose(p, tc[i])
+        J = np.zeros((2, 3))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = 1e-5 * abs(z)
+            J[:, k] = (pi(p + e) - pi(p - e)) / (2 * e[k])
+        S2 = J @ W @ Sig @ W.T @ J.T + 0.3 * np.eye(2)
+        cov = pr["cov2d"][i]
+        got = np.array([[cov[0], cov[1]], [cov[1], cov[2]]])
+        np.testing.assert_allclose(got, S2, rtol=1e-6, atol=1e-9 * np.abs(S2).max())
+        a, b, c = pr["conic"][i]
+        np.testing.assert_allclose(np.array([[a, b], [b, c]]) @ got, np.eye(2), atol=1e-10)
+    assert clamped > 0
+
+
+def test_projection_culls(oracle):
+    sc = scenes.make_scene("uniform", 6, 16, 0)
+    sc["means"][0] = (0.0, 0.0, -3.5)           # behind the camera
+    sc["means"][1] = (0.0, 0.0, -2.85)          # in front of the near plane (z = 0.15)
+    sc["opacity"][2] = np.float32(1.0 / 256)    # below alpha_min
+    sc["log_scales"][3, 0] = np.nan             # not finite
+    cam = scenes.make_camera(32, 32)
+    pr = oracle.project(sc, cam, scenes.render_config(0))
+    np.testing.assert_array_equal(pr["valid"], [False, False, False, False, True, True])
+
+
+# ---------------------------------------------------------------------------
+# P11: pixel mapping between resolutions
+# ---------------------------------------------------------------------------
+def test_lowres_nodes_equal_highres_render(oracle):
+    """For an odd factor s (dilation scaled by s^2), the low-res render at node
+    (k, m) equals the direct high-res render at (s k + (s-1)/2, s m + (s-1)/2),
+    derivatives scaled by s per axis; the upscaled image agrees there too."""
+    s = 3
+    sc = scenes.make_scene("uniform", 3000, 17, 0)
+    base = scenes.make_camera(32, 24)
+    lo = dict(base, fx=40.0, fy=40.0, cx=15.5, cy=11.5)
+    hi = scenes.scale_camera(lo, 96, 72)
+    assert (hi["fx"], hi["cx"], hi["cy"]) == (120.0, 47.5, 35.5)
+    cfg_lo = scenes.render_config(0, dilation=0.0625)
+    cfg_hi = scenes.render_config(0, dilation=0.5625)
+    rl = oracle.render(sc, lo, cfg_lo)["img"]
+    pr = oracle.project(sc, hi, cfg_hi)
+    order = oracle.depth_order(pr)
+    yy, xx = np.meshgrid(np.arange(24) * s + 1.0, np.arange(32) * s + 1.0, indexing="ij")
+    rh = oracle.composite(pr, order, cfg_hi, xx.reshape(-1), yy.reshape(-1))["out"].reshape(24, 32, 12)
+    scale = np.array([1] * 3 + [s] * 6 + [s * s] * 3, float)
+    np.testing.assert_allclose(rh * scale, rl, atol=1e-10)
+    up = oracle.upscale(rl, 96, 72)
+    np.testing.assert_allclose(up[1::3, 1::3], rh[..., :3], atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# support box: brute force over the image
+# ---------------------------------------------------------------------------
+def test_support_box_is_exact_and_conservative(oracle):
+    sc = scenes.make_scene("uniform", 300, 18, 0)
+    sc["log_scales"] += np.float32(1.0)
+    cam = scenes.make_camera(64, 64)
+    cfg = scenes.render_config(0)
+    pr = oracle.project(sc, cam, cfg)
+    yy, xx = np.meshgrid(np.arange(64.0), np.arange(64.0), indexing="ij")
+    X, Y = xx.reshape(-1), yy.reshape(-1)
+    for i in np.nonzero(pr["valid"])[0][:120]:
+        res = oracle.composite(pr, np.array([i]), cfg, X, Y)
+        hit = res["n_blend"] == 1
+        b = pr["bbox"][i]
+        inside = (X >= b[0]) & (X <= b[1]) & (Y >= b[2]) & (Y <= b[3])
+        assert not (hit & ~inside).any()
+        # the box is tight: at the ellipse's extreme point alpha == alpha_min
+        S = pr["cov2d"][i]
+        L = np.log(pr["opacity"][i] / float(np.float32(cfg["alpha_min"])))
+        d = np.array([S[0], S[1]]) * np.sqrt(2 * L / S[0])
+        p = pr["mean2d"][i] + d
+        np.testing.assert_allclose(p[0], b[1], rtol=1e-12)
+        at = oracle.composite(pr, np.array([i]), cfg, [p[0]], [p[1]], tie_alpha=1e-9)
+        assert at["n_amb"][0] == 1
+
+
+# ---------------------------------------------------------------------------
+# near-tie enumeration: each variant is the walk with that decision inverted
+# ---------------------------------------------------------------------------
+def test_near_tie_variants(oracle):
+    """A fragment whose alpha sits within the tie margin of alpha_min yields
+    two valid results: with and without that fragment."""
+    amin = float(np.float32(1.0 / 255.0))
+    sig = 0.6
+    # place the pixel where Gaussian 1 has alpha = amin (1 + 1e-6)
+    a = 0.5
+    r2 = -2 * np.log(amin * (1 + 1e-6) / sig) / a
+    pts = [[0.0, 0.0], [np.sqrt(r2), 0.0], [0.3, 0.2]]
+    pr = _proj(pts, [[0.4, 0.0, 0.4], [a, 0.0, a], [0.9, 0.1, 0.7]], [0.5, sig, 0.7],
+               [[0.2, 0.4, 0.6], [0.9, 0.1, 0.3], [0.5, 0.5, 0.5]])
+    cfg = scenes.render_config(0)
+    res = oracle.composite(pr, np.array([0, 1, 2]), cfg, [0.0], [0.0], variants=True)
+    assert res["n_amb"][0] == 1 and res["n_var"][0] == 2
+    with_all = oracle.composite(pr, np.array([0, 1, 2]), cfg, [0.0], [0.0])["out"][0]
+    without = oracle.composite(pr, np.array([0, 2]), cfg, [0.0], [0.0])["out"][0]
+    np.testing.assert_allclose(res["variants"][0, 0], with_all, atol=1e-15)
+    np.testing.assert_allclose(res["variants"][0, 1], without, atol=1e-15)
+    assert np.abs(with_all - without).max() > 1e-3
