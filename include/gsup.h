@@ -1,0 +1,185 @@
+/*
+ * gsup.h -- C ABI of the MI355X (gfx950) implementation of gradient-aware
+ * upscaling of 3D Gaussian Splatting images (Niedermayr, Neuhauser,
+ * Westermann, arXiv 2503.14171).
+ *
+ * One camera view goes through four calls:
+ *
+ *   gs_project          3D Gaussians -> 2D splats: EWA projection of the
+ *                       covariance, view-dependent SH colour, depth, and the
+ *                       rectangle of screen tiles the splat can reach.
+ *   gs_bin_sort         splats -> one front-to-back index list per tile.
+ *   gs_raster_grad      tile lists -> low-res colour I and its analytical
+ *                       screen-space derivatives dI/dx, dI/dy, d2I/dxdy.
+ *   gs_upscale_hermite  low-res colour + derivatives -> high-res image, one
+ *                       bicubic Hermite patch per low-res pixel cell.
+ *
+ * Conventions shared by every call
+ *   - Array arguments are DEVICE pointers (HBM), owned by the caller, dense
+ *     row-major, little-endian, FP32 unless stated.  The library never
+ *     allocates, frees or keeps device memory between calls.
+ *   - Structs (gs_camera, gs_raster_cfg) and scalar out-parameters
+ *     (n_pairs) live in HOST memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Every call only enqueues work on that stream and returns, except
+ *     gs_bin_sort, which waits on the stream once to read the pair count.
+ *   - Arguments are validated on the host before anything is enqueued.  On
+ *     any error the call returns a non-zero gs_status, enqueues nothing (or
+ *     nothing further), and gs_last_error_message() describes the problem.
+ *   - Image coordinates: x = column (right), y = row (down); the centre of
+ *     pixel (x, y) is the point (x, y); the image spans [-1/2, W-1/2] in x.
+ *   - Camera: pinhole with OpenCV axes (+x right, +y down, +z forward).
+ *   - Calls are reentrant; concurrent calls on different streams must use
+ *     distinct output and workspace buffers.
+ */
+#ifndef GSUP_H
+#define GSUP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARGUMENT = 1, /* a pointer, size or setting is out of range */
+  GS_ERR_CAPACITY = 2,         /* gs_bin_sort: more (tile, splat) pairs than `capacity` */
+  GS_ERR_HIP = 3,              /* the HIP runtime reported an error */
+  GS_ERR_UNSUPPORTED = 4       /* a setting this build does not implement */
+} gs_status;
+
+/* Pinhole camera.  A world point p maps to camera space t = R p + t_W with
+ * view = [R | t_W] (row-major 3x4), and to the image point
+ * (fx t.x / t.z + cx, fy t.y / t.z + cy). */
+typedef struct gs_camera {
+  int32_t width, height; /* raster size in pixels, >= 1 */
+  float fx, fy;          /* focal lengths in pixels, > 0 */
+  float cx, cy;          /* principal point in pixels */
+  float view[12];        /* world -> camera [R | t_W], row-major */
+  float cam_pos[3];      /* camera centre in world space (SH view direction) */
+  float near_plane;      /* Gaussians with camera z <= near_plane are culled, > 0 */
+} gs_camera;
+
+/* Render settings.  The paper fixes none of these numbers; see each field. */
+typedef struct gs_raster_cfg {
+  int32_t tile_size; /* square screen tile edge in pixels: 8 or 16 */
+  int32_t sh_degree; /* degree of the SH colour, 0..3 */
+  float dilation;    /* px^2 added to the 2D covariance diagonal (low-pass), >= 0; 3DGS uses 0.3 */
+  float alpha_min;   /* fragments with alpha < alpha_min are skipped, in (0, alpha_max) */
+  float alpha_max;   /* alpha > alpha_max is clamped to alpha_max (zero screen derivatives), < 1 */
+  float t_min;       /* a pixel stops once its transmittance after a blend is < t_min, in (0, 1) */
+  float bg[3];       /* background colour behind the last fragment */
+} gs_raster_cfg;
+
+/* A projected Gaussian (48 bytes, 16-byte aligned).  The 2D mean is kept in
+ * FP64 so that pixel-relative offsets stay exact at 4K image coordinates. */
+typedef struct gs_splat {
+  double mean[2];  /* image-plane mean (pixels) */
+  float conic[3];  /* (a, b, c): inverse of the dilated 2D covariance [[a, b], [b, c]] */
+  float opacity;   /* sigma in [alpha_min, 1] */
+  float rgb[3];    /* view-dependent colour, max(0, sum_lm Y_lm k_lm + 1/2) */
+  float support;   /* 2 ln(sigma / alpha_min): alpha >= alpha_min <=> d^T Q d <= support */
+} gs_splat;
+
+/* Number of tiles of a width x height raster: ceil(W/ts) * ceil(H/ts). */
+int64_t gs_num_tiles(int32_t width, int32_t height, int32_t tile_size);
+
+/* gs_project -- EWA projection and SH colour of n Gaussians.
+ * Follows Sec. "Differentiable 3D Gaussian Splatting" (2D covariance
+ * Sigma' = J W Sigma W^T J^T, Gaussians ordered by the depth of their mean,
+ * SH view-dependent colour).
+ *
+ * Inputs (device, FP32):
+ *   means [n,3]       world-space centres mu
+ *   log_scales [n,3]  per-axis log standard deviations; Sigma = R S S^T R^T, S = diag(exp(.))
+ *   quats [n,4]       rotation quaternions (w, x, y, z), normalised here
+ *   opacity [n]       sigma in [0, 1] (after the sigmoid)
+ *   sh [n,(d+1)^2,3]  SH coefficients, real orthonormal basis ordered l^2+l+m
+ *                     (graphics sign convention), d = cfg->sh_degree
+ * Outputs (device):
+ *   splats [n]        gs_splat records (zeroed when culled)
+ *   depth [n]         camera-space z rounded to FP32 (the sort key)
+ *   rect [n,4] int32  tile rectangle [tx0, ty0, tx1, ty1) that holds every pixel
+ *                     with alpha >= alpha_min; all zero when culled or off-screen
+ * A Gaussian is culled when an input is not finite, its camera z <= near_plane,
+ * its 2D covariance is not positive definite, or sigma < alpha_min.
+ * The Jacobian J is evaluated with the mean's direction clamped to 1.3x the
+ * half field of view.  n == 0 is a no-op. */
+gs_status gs_project(int64_t n, const float* means, const float* log_scales, const float* quats,
+                     const float* opacity, const float* sh, const gs_camera* cam,
+                     const gs_raster_cfg* cfg, gs_splat* splats, float* depth, int32_t* rect,
+                     void* stream);
+
+/* Bytes of device workspace gs_bin_sort needs for n splats and `capacity` pairs. */
+size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* cam,
+                                  const gs_raster_cfg* cfg);
+
+/* gs_bin_sort -- per-tile front-to-back lists (the depth order of
+ * Sec. "Differentiable 3D Gaussian Splatting", restricted to each tile).
+ *
+ * Inputs (device): depth [n] and rect [n,4] from gs_project.
+ * Outputs:
+ *   sorted_ids [capacity] int32  (device) splat indices; tile t's list is
+ *                               sorted_ids[tile_ranges[2t] .. tile_ranges[2t+1]),
+ *                               ordered by (FP32 depth, index)
+ *   tile_ranges [T,2] int32     (device) [start, end) per tile, T = gs_num_tiles(..)
+ *   n_pairs                     (HOST) number of (tile, splat) pairs K
+ * workspace: device scratch of at least gs_bin_sort_workspace_size(n, capacity, ..)
+ * bytes, 256-byte aligned; its contents are undefined after the call.
+ * If K > capacity the call returns GS_ERR_CAPACITY with *n_pairs = K and the
+ * outputs undefined; the caller grows the buffers and calls again.
+ * Waits on `stream` once (to read K).  K must stay below 2^31. */
+gs_status gs_bin_sort(int64_t n, const float* depth, const int32_t* rect, const gs_camera* cam,
+                      const gs_raster_cfg* cfg, int64_t capacity, int32_t* sorted_ids,
+                      int32_t* tile_ranges, int64_t* n_pairs, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* gs_raster_grad -- front-to-back alpha blending of every pixel's tile list,
+ * with the analytical screen-space derivatives of the blended colour.
+ * Follows Sec. "Image Gradient Based Upscaling" (3DGS image gradients: the
+ * derivatives of I = sum_i T_i alpha_i c_i and the iterative transmittance
+ * derivatives) and Suppl. "3DGS Gradient Computation - Forward pass".
+ * Per fragment alpha = sigma exp(-1/2 d^T Q d), d = pixel - mean; skipped if
+ * alpha < alpha_min, clamped (zero derivatives) if alpha > alpha_max; a pixel
+ * stops after the blend that takes its transmittance below t_min.
+ *
+ * Inputs (device): splats [n], sorted_ids, tile_ranges from gs_bin_sort (for
+ * the same camera and tile size).
+ * Output (device) `out`, per pixel of the cam->width x cam->height raster:
+ *   want_grads != 0: [H, W, 12] = (I rgb, dI/dx rgb, dI/dy rgb, d2I/dxdy rgb),
+ *                    derivatives per pixel (per pixel^2 for the mixed one)
+ *   want_grads == 0: [H, W, 3]  = I rgb (plain 3DGS compositing)
+ * n_blend (device, optional, may be NULL): [H, W] int32 blended fragments per pixel. */
+gs_status gs_raster_grad(const gs_splat* splats, const int32_t* sorted_ids,
+                         const int32_t* tile_ranges, const gs_camera* cam,
+                         const gs_raster_cfg* cfg, int32_t want_grads, float* out,
+                         int32_t* n_blend, void* stream);
+
+/* gs_upscale_hermite -- bicubic Hermite upscaling from values and derivatives.
+ * Follows Sec. "Image Gradient Based Upscaling" (F = C A C^T, patch
+ * p(x,y) = [1 x x^2 x^3] A [1 y y^2 y^3]^T, one A per low-res cell) and
+ * Suppl. "Spline Image Interpolation".
+ * High-res pixel (X, Y) samples the low-res point u = (X + 1/2) w / W - 1/2,
+ * v = (Y + 1/2) h / H - 1/2 with the patch of cell (i, j) = (clamp(floor u, 0,
+ * w-2), clamp(floor v, 0, h-2)) at local (u - i, v - j) (extrapolated at the
+ * border).  Any real factors W/w >= 1, H/h >= 1 (independent per axis).
+ *
+ * in  [h, w, 12] (device): (I rgb, I_x rgb, I_y rgb, I_xy rgb) as written by
+ *     gs_raster_grad, derivatives per low-res pixel; w, h >= 2.
+ * out [H, W, 3]  (device): upscaled rgb.  `in` and `out` must not overlap. */
+gs_status gs_upscale_hermite(const float* in, int32_t w, int32_t h, float* out, int32_t W,
+                             int32_t H, void* stream);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* gs_last_error_message(void);
+
+/* Library version string. */
+const char* gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSUP_H */

@@ -1,0 +1,174 @@
+"""ctypes binding of libgsup.so (include/gsup.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls and takes torch
+tensors for the device arrays; torch provides device memory and the current
+HIP stream, every computation runs in the library's HIP kernels.  A non-zero
+status raises :class:`GsError` carrying the library's message.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first: libgsup then binds to the HIP runtime torch already mapped
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgsup.so")
+
+GS_OK = 0
+GS_ERR_INVALID_ARGUMENT = 1
+GS_ERR_CAPACITY = 2
+GS_ERR_HIP = 3
+GS_ERR_UNSUPPORTED = 4
+
+SPLAT_FLOATS = 12  # gs_splat: 48 bytes = 12 x 4
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, message: str, n_pairs: int | None = None):
+        super().__init__(f"[gs status {status}] {message}")
+        self.status = status
+        self.n_pairs = n_pairs
+
+
+class GsCamera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("view", ctypes.c_float * 12), ("cam_pos", ctypes.c_float * 3),
+                ("near_plane", ctypes.c_float)]
+
+
+class GsRasterCfg(ctypes.Structure):
+    _fields_ = [("tile_size", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
+                ("dilation", ctypes.c_float), ("alpha_min", ctypes.c_float),
+                ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
+                ("bg", ctypes.c_float * 3)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                              "`python -m paper_2503_14171_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(_LIB_PATH)
+        P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        cam_p, cfg_p = ctypes.POINTER(GsCamera), ctypes.POINTER(GsRasterCfg)
+        L.gs_num_tiles.argtypes = [i32, i32, i32]
+        L.gs_num_tiles.restype = i64
+        L.gs_project.argtypes = [i64, P, P, P, P, P, cam_p, cfg_p, P, P, P, P]
+        L.gs_project.restype = ctypes.c_int
+        L.gs_bin_sort_workspace_size.argtypes = [i64, i64, cam_p, cfg_p]
+        L.gs_bin_sort_workspace_size.restype = sz
+        L.gs_bin_sort.argtypes = [i64, P, P, cam_p, cfg_p, i64, P, P, ctypes.POINTER(i64), P, sz, P]
+        L.gs_bin_sort.restype = ctypes.c_int
+        L.gs_raster_grad.argtypes = [P, P, P, cam_p, cfg_p, i32, P, P, P]
+        L.gs_raster_grad.restype = ctypes.c_int
+        L.gs_upscale_hermite.argtypes = [P, i32, i32, P, i32, i32, P]
+        L.gs_upscale_hermite.restype = ctypes.c_int
+        L.gs_last_error_message.restype = ctypes.c_char_p
+        L.gs_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def camera(cam: dict) -> GsCamera:
+    c = GsCamera()
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.fx, c.fy, c.cx, c.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    c.view[:] = [float(v) for v in torch.as_tensor(cam["view"]).reshape(12).tolist()]
+    c.cam_pos[:] = [float(v) for v in torch.as_tensor(cam["cam_pos"]).reshape(3).tolist()]
+    c.near_plane = float(cam["near_plane"])
+    return c
+
+
+def raster_cfg(cfg: dict) -> GsRasterCfg:
+    c = GsRasterCfg()
+    c.tile_size = int(cfg["tile_size"])
+    c.sh_degree = int(cfg["sh_degree"])
+    c.dilation = float(cfg["dilation"])
+    c.alpha_min, c.alpha_max, c.t_min = float(cfg["alpha_min"]), float(cfg["alpha_max"]), float(cfg["t_min"])
+    c.bg[:] = [float(v) for v in cfg["bg"]]
+    return c
+
+
+def _ptr(t: torch.Tensor | None, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{dtype} tensor expected, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check(status: int, n_pairs: int | None = None):
+    if status != GS_OK:
+        raise GsError(status, lib().gs_last_error_message().decode(), n_pairs)
+
+
+def gs_version() -> str:
+    return lib().gs_version().decode()
+
+
+def gs_num_tiles(width: int, height: int, tile_size: int) -> int:
+    return int(lib().gs_num_tiles(width, height, tile_size))
+
+
+def gs_project(means, log_scales, quats, opacity, sh, cam: dict, cfg: dict, splats, depth, rect,
+               stream=None) -> None:
+    """Project n Gaussians; outputs splats [n,12] f32 (gs_splat records),
+    depth [n] f32, rect [n,4] i32."""
+    n = means.shape[0]
+    f = torch.float32
+    _check(lib().gs_project(n, _ptr(means, f), _ptr(log_scales, f), _ptr(quats, f), _ptr(opacity, f),
+                            _ptr(sh, f), ctypes.byref(camera(cam)), ctypes.byref(raster_cfg(cfg)),
+                            _ptr(splats, f), _ptr(depth, f), _ptr(rect, torch.int32), _stream(stream)))
+
+
+def gs_bin_sort_workspace_size(n: int, capacity: int, cam: dict, cfg: dict) -> int:
+    return int(lib().gs_bin_sort_workspace_size(n, capacity, ctypes.byref(camera(cam)),
+                                                ctypes.byref(raster_cfg(cfg))))
+
+
+def gs_bin_sort(n: int, depth, rect, cam: dict, cfg: dict, capacity: int, sorted_ids, tile_ranges,
+                workspace, stream=None) -> int:
+    """Per-tile lists; returns the pair count K (raises GsError with .n_pairs if K > capacity)."""
+    k = ctypes.c_int64(0)
+    st = lib().gs_bin_sort(n, _ptr(depth, torch.float32), _ptr(rect, torch.int32),
+                           ctypes.byref(camera(cam)), ctypes.byref(raster_cfg(cfg)), capacity,
+                           _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
+                           ctypes.byref(k), _ptr(workspace, torch.uint8), workspace.numel(),
+                           _stream(stream))
+    _check(st, int(k.value))
+    return int(k.value)
+
+
+def gs_raster_grad(splats, sorted_ids, tile_ranges, cam: dict, cfg: dict, want_grads: bool, out,
+                   n_blend=None, stream=None) -> None:
+    _check(lib().gs_raster_grad(_ptr(splats, torch.float32), _ptr(sorted_ids, torch.int32),
+                                _ptr(tile_ranges, torch.int32), ctypes.byref(camera(cam)),
+                                ctypes.byref(raster_cfg(cfg)), 1 if want_grads else 0,
+                                _ptr(out, torch.float32), _ptr(n_blend, torch.int32), _stream(stream)))
+
+
+def gs_upscale_hermite(inp, out, stream=None) -> None:
+    """inp [h, w, 12] -> out [H, W, 3]."""
+    h, w = inp.shape[0], inp.shape[1]
+    H, W = out.shape[0], out.shape[1]
+    if inp.shape[2] != 12 or out.shape[2] != 3:
+        raise ValueError("inp must be [h, w, 12] and out [H, W, 3]")
+    _check(lib().gs_upscale_hermite(_ptr(inp, torch.float32), w, h, _ptr(out, torch.float32), W, H,
+                                    _stream(stream)))

@@ -1,0 +1,255 @@
+// gs_project kernel: EWA projection of 3D Gaussians and their SH colour.
+//
+// Sec. "Differentiable 3D Gaussian Splatting" of arXiv 2503.14171: a 3D
+// Gaussian (mean mu, covariance Sigma from scale and rotation, opacity sigma,
+// SH colour coefficients) projects to a 2D Gaussian with covariance
+// Sigma' = J W Sigma W^T J^T, J the Jacobian of the local affine
+// approximation of the perspective map.
+//
+// One thread per Gaussian.  The geometry is evaluated in FP64: MI355X runs
+// FP64 vector FMAs at the FP32 rate and the kernel is bound by HBM traffic
+// (236 B/Gaussian at SH degree 3), so the extra precision is free; it keeps
+// the FP32-stored conic and the FP64-stored mean accurate to the last bit,
+// which the derivative buffers need (their sensitivity to the mean grows as
+// 1/sigma_px^3).
+#include <cmath>
+
+#include "gsup_internal.h"
+
+namespace gsup {
+namespace {
+
+// Widening of the exact alpha_min support box, in pixels, so that FP32
+// rounding in the rasterizer's alpha test can never reach outside the tiles.
+constexpr double kRectMargin = 0.25;
+// The Jacobian is evaluated at the mean with its direction clamped to this
+// multiple of the half field of view (keeps off-screen footprints finite).
+constexpr double kFrustumClamp = 1.3;
+
+struct ProjParams {
+  int64_t n;
+  int32_t width, height, tile;
+  int32_t sh_degree;
+  double fx, fy, cx, cy;
+  double V[12];
+  double cam[3];
+  double near_plane;
+  double dilation;
+  double alpha_min;
+  double limx, limy;
+};
+
+// Real orthonormal SH basis (graphics sign convention, Condon-Shortley phase
+// kept), ordered l^2 + l + m, evaluated as polynomials of the unit direction.
+// Constants: K0 = 1/(2 sqrt(pi)); K1 = sqrt(3/(4 pi)); K2a = sqrt(15/pi)/2,
+// K2b = sqrt(5/pi)/4, K2c = sqrt(15/pi)/4; K3a = sqrt(35/(2 pi))/4,
+// K3b = sqrt(105/pi)/2, K3c = sqrt(21/(2 pi))/4, K3d = sqrt(7/pi)/4,
+// K3e = sqrt(105/pi)/4.
+template <int DEG>
+__device__ __forceinline__ void sh_eval(double x, double y, double z, double* Y) {
+  const double K0 = 0.28209479177387814, K1 = 0.4886025119029199;
+  const double K2a = 1.0925484305920792, K2b = 0.31539156525252005, K2c = 0.5462742152960396;
+  const double K3a = 0.5900435899266435, K3b = 2.890611442640554, K3c = 0.4570457994644658,
+               K3d = 0.3731763325901154, K3e = 1.445305721320277;
+  Y[0] = K0;
+  if (DEG < 1) return;
+  Y[1] = -K1 * y;
+  Y[2] = K1 * z;
+  Y[3] = -K1 * x;
+  if (DEG < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = K2a * x * y;
+  Y[5] = -K2a * y * z;
+  Y[6] = K2b * (2.0 * zz - xx - yy);
+  Y[7] = -K2a * x * z;
+  Y[8] = K2c * (xx - yy);
+  if (DEG < 3) return;
+  Y[9] = -K3a * y * (3.0 * xx - yy);
+  Y[10] = K3b * x * y * z;
+  Y[11] = -K3c * y * (4.0 * zz - xx - yy);
+  Y[12] = K3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -K3c * x * (4.0 * zz - xx - yy);
+  Y[14] = K3e * z * (xx - yy);
+  Y[15] = -K3a * x * (xx - 3.0 * yy);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float* __restrict__ means,
+                                                      const float* __restrict__ log_scales,
+                                                      const float* __restrict__ quats,
+                                                      const float* __restrict__ opacity,
+                                                      const float* __restrict__ sh,
+                                                      gs_splat* __restrict__ splats,
+                                                      float* __restrict__ depth_out,
+                                                      int4* __restrict__ rect_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+
+  const double mu0 = means[3 * i], mu1 = means[3 * i + 1], mu2 = means[3 * i + 2];
+  const double ls0 = log_scales[3 * i], ls1 = log_scales[3 * i + 1], ls2 = log_scales[3 * i + 2];
+  const float4 q4 = reinterpret_cast<const float4*>(quats)[i];
+  const float sig = opacity[i];
+
+  // SH coefficients: 3 * nb floats per Gaussian.
+  float coef[3 * nb];
+  const float* shg = sh + (int64_t)3 * nb * i;
+  if constexpr ((3 * nb) % 4 == 0) {
+    const float4* s4 = reinterpret_cast<const float4*>(shg);
+#pragma unroll
+    for (int k = 0; k < 3 * nb / 4; ++k) {
+      const float4 v = s4[k];
+      coef[4 * k] = v.x;
+      coef[4 * k + 1] = v.y;
+      coef[4 * k + 2] = v.z;
+      coef[4 * k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3 * nb; ++k) coef[k] = shg[k];
+  }
+
+  bool ok = isfinite(sig) && isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(ls0) &&
+            isfinite(ls1) && isfinite(ls2) && isfinite(q4.x) && isfinite(q4.y) &&
+            isfinite(q4.z) && isfinite(q4.w);
+#pragma unroll
+  for (int k = 0; k < 3 * nb; ++k) ok = ok && isfinite(coef[k]);
+
+  const double* V = p.V;
+  // camera-space position, summed left to right (products of FP32 values are
+  // exact in FP64, so the depth is the correctly ordered sum)
+  const double t0 = ((V[0] * mu0 + V[1] * mu1) + V[2] * mu2) + V[3];
+  const double t1 = ((V[4] * mu0 + V[5] * mu1) + V[6] * mu2) + V[7];
+  const double t2 = ((V[8] * mu0 + V[9] * mu1) + V[10] * mu2) + V[11];
+  const double qn2 = (double)q4.x * q4.x + (double)q4.y * q4.y + (double)q4.z * q4.z +
+                     (double)q4.w * q4.w;
+  ok = ok && (t2 > p.near_plane) && (qn2 > 0.0) && ((double)sig >= p.alpha_min);
+
+  float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0;
+  double2 m2 = make_double2(0.0, 0.0);
+  int4 rect = make_int4(0, 0, 0, 0);
+  float dep = INFINITY;
+
+  if (ok) {
+    // rotation of the unit quaternion (w, x, y, z)
+    const double qi = 1.0 / sqrt(qn2);
+    const double w = q4.x * qi, x = q4.y * qi, y = q4.z * qi, z = q4.w * qi;
+    double R[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                      {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                      {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+    const double s2[3] = {exp(2.0 * ls0), exp(2.0 * ls1), exp(2.0 * ls2)};
+    // M = J W (2x3); Sigma' = M R S^2 R^T M^T = (M R) S^2 (M R)^T
+    const double tz = t2;
+    const double ux = fmin(p.limx, fmax(-p.limx, t0 / tz)) * tz;
+    const double uy = fmin(p.limy, fmax(-p.limy, t1 / tz)) * tz;
+    const double j00 = p.fx / tz, j02 = -p.fx * ux / (tz * tz);
+    const double j11 = p.fy / tz, j12 = -p.fy * uy / (tz * tz);
+    double M[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      M[0][c] = j00 * V[c] + j02 * V[8 + c];
+      M[1][c] = j11 * V[4 + c] + j12 * V[8 + c];
+    }
+    double P[2][3];  // P = M R
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P[r][c] = M[r][0] * R[0][c] + M[r][1] * R[1][c] + M[r][2] * R[2][c];
+    double sxx = p.dilation, sxy = 0.0, syy = p.dilation;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      sxx += P[0][k] * P[0][k] * s2[k];
+      sxy += P[0][k] * P[1][k] * s2[k];
+      syy += P[1][k] * P[1][k] * s2[k];
+    }
+    const double det = sxx * syy - sxy * sxy;
+    if (det > 0.0) {
+      const double id = 1.0 / det;
+      const double mx = p.fx * t0 / tz + p.cx;
+      const double my = p.fy * t1 / tz + p.cy;
+      const double L = log((double)sig / p.alpha_min);
+      const double rx = sqrt(2.0 * L * sxx), ry = sqrt(2.0 * L * syy);
+      double x0 = ceil(mx - rx - kRectMargin), x1 = floor(mx + rx + kRectMargin);
+      double y0 = ceil(my - ry - kRectMargin), y1 = floor(my + ry + kRectMargin);
+      x0 = fmax(x0, 0.0);
+      y0 = fmax(y0, 0.0);
+      x1 = fmin(x1, (double)(p.width - 1));
+      y1 = fmin(y1, (double)(p.height - 1));
+      if (x0 <= x1 && y0 <= y1) {
+        rect = make_int4((int)x0 / p.tile, (int)y0 / p.tile, (int)x1 / p.tile + 1,
+                         (int)y1 / p.tile + 1);
+      }
+      // view-dependent colour
+      double dx = mu0 - p.cam[0], dy = mu1 - p.cam[1], dz = mu2 - p.cam[2];
+      const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+      if (dn > 0.0) {
+        dx /= dn;
+        dy /= dn;
+        dz /= dn;
+      } else {
+        dx = 0.0;
+        dy = 0.0;
+        dz = 1.0;
+      }
+      double Y[nb];
+      sh_eval<DEG>(dx, dy, dz, Y);
+      double col[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+      for (int k = 0; k < nb; ++k) {
+        col[0] += Y[k] * (double)coef[3 * k];
+        col[1] += Y[k] * (double)coef[3 * k + 1];
+        col[2] += Y[k] * (double)coef[3 * k + 2];
+      }
+      m2 = make_double2(mx, my);
+      w0 = make_float4((float)(syy * id), (float)(-sxy * id), (float)(sxx * id), sig);
+      w1 = make_float4((float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0),
+                       (float)fmax(col[2], 0.0), (float)(2.0 * L));
+      dep = (float)t2;
+    }
+  }
+  double2* sp = reinterpret_cast<double2*>(splats + i);
+  sp[0] = m2;
+  float4* sf = reinterpret_cast<float4*>(splats + i);
+  sf[1] = w0;
+  sf[2] = w1;
+  depth_out[i] = dep;
+  rect_out[i] = rect;
+}
+
+}  // namespace
+
+hipError_t launch_project(int64_t n, const float* means, const float* log_scales,
+                          const float* quats, const float* opacity, const float* sh,
+                          const gs_camera& cam, const gs_raster_cfg& cfg, gs_splat* splats,
+                          float* depth, int32_t* rect, hipStream_t stream) {
+  ProjParams p;
+  p.n = n;
+  p.width = cam.width;
+  p.height = cam.height;
+  p.tile = cfg.tile_size;
+  p.sh_degree = cfg.sh_degree;
+  p.fx = cam.fx;
+  p.fy = cam.fy;
+  p.cx = cam.cx;
+  p.cy = cam.cy;
+  for (int k = 0; k < 12; ++k) p.V[k] = cam.view[k];
+  for (int k = 0; k < 3; ++k) p.cam[k] = cam.cam_pos[k];
+  p.near_plane = cam.near_plane;
+  p.dilation = cfg.dilation;
+  p.alpha_min = cfg.alpha_min;
+  p.limx = kFrustumClamp * (0.5 * cam.width) / (double)cam.fx;
+  p.limy = kFrustumClamp * (0.5 * cam.height) / (double)cam.fy;
+  const int threads = 256;
+  const int64_t blocks = ceil_div(n, threads);
+  int4* r4 = reinterpret_cast<int4*>(rect);
+  const dim3 g((unsigned)blocks), b(threads);
+  switch (cfg.sh_degree) {
+    case 0: project_kernel<0><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
+    case 1: project_kernel<1><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
+    case 2: project_kernel<2><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
+    default: project_kernel<3><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsup

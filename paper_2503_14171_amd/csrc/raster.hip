@@ -1,0 +1,182 @@
+// gs_raster_grad: tile rasterizer that blends each pixel's splats front to
+// back and carries the analytical screen-space derivatives of the colour.
+//
+// Sec. "Image Gradient Based Upscaling" (3DGS image gradients) and Suppl.
+// "3DGS Gradient Computation - Forward pass" of arXiv 2503.14171: the image
+// I = sum_i T_i alpha_i c_i with alpha_i = sigma_i exp(g_i) is differentiated
+// in x and y; the transmittance derivatives follow an iterative recurrence
+// that runs inside the blending loop.  With A the accumulated alpha, the
+// paper's recurrences for B_i, A_i and their x, y, xy derivatives are carried
+// here in terms of T = 1 - A (T_x = -A_x, ...), which keeps T accurate in FP32
+// where A approaches one:
+//     k    = T alpha                          (weight of this fragment)
+//     k_x  = T alpha_x + T_x alpha,   k_y likewise
+//     k_xy = T alpha_xy + T_x alpha_y + T_y alpha_x + T_xy alpha
+//     B_* += c k_*,   T_* -= k_*       for * in {_, x, y, xy}
+// with alpha_x = -alpha u, alpha_y = -alpha v, alpha_xy = alpha (u v - b),
+// (u, v) = Q d, d = pixel - mean, Q = [[a, b], [b, c]] the conic.
+//
+// Work decomposition (gfx950): one workgroup per screen tile, one pixel per
+// lane (8x8 tile = one wave64, 16x16 tile = four).  The tile's splats stream
+// through LDS in batches of one splat per lane; every lane reads the same LDS
+// record (broadcast, no bank conflicts).  A lane whose transmittance dropped
+// below t_min leaves the batch loop; the wave's exec mask then shrinks and the
+// wave leaves once every lane is done, and the workgroup stops fetching
+// batches once a barrier count shows no live pixel.  Splat means are held in
+// FP64 and turned into tile-relative FP32 offsets when staged into LDS, so
+// pixel - mean is exact at any image coordinate.
+#include "gsup_internal.h"
+
+namespace gsup {
+namespace {
+
+struct RasterParams {
+  int32_t width, height, tiles_x;
+  int64_t tiles;
+  float alpha_max, t_min;
+  float bg[3];
+};
+
+template <int TILE, bool GRAD>
+__global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
+                                                            const gs_splat* __restrict__ splats,
+                                                            const int32_t* __restrict__ ids,
+                                                            const int2* __restrict__ ranges,
+                                                            float* __restrict__ out,
+                                                            int32_t* __restrict__ n_blend) {
+  constexpr int NT = TILE * TILE;
+  constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
+  __shared__ float4 s_a[NT];  // mean x, mean y (tile-relative), conic a, conic b
+  __shared__ float4 s_b[NT];  // conic c, log2 sigma, support, red
+  __shared__ float2 s_c[NT];  // green, blue
+
+  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+  if (tile >= p.tiles) return;
+  const int tx = (int)(tile % p.tiles_x), ty = (int)(tile / p.tiles_x);
+  const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+  const int px = tx * TILE + lx, py = ty * TILE + ly;
+  const bool inside = px < p.width && py < p.height;
+  const float fx = (float)lx, fy = (float)ly;
+  const double ox = (double)tx * TILE, oy = (double)ty * TILE;
+  const int2 rg = ranges[tile];
+
+  bool done = !inside;
+  float T = 1.f, Tx = 0.f, Ty = 0.f, Txy = 0.f;
+  float B0 = 0.f, B1 = 0.f, B2 = 0.f;
+  float Bx0 = 0.f, Bx1 = 0.f, Bx2 = 0.f, By0 = 0.f, By1 = 0.f, By2 = 0.f;
+  float Bxy0 = 0.f, Bxy1 = 0.f, Bxy2 = 0.f;
+  int nb = 0;
+
+  for (int base = rg.x; base < rg.y; base += NT) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int idx = base + (int)threadIdx.x;
+    if (idx < rg.y) {
+      const float4* s = reinterpret_cast<const float4*>(splats + ids[idx]);
+      const double2 m = *reinterpret_cast<const double2*>(s);
+      const float4 q = s[1];  // a, b, c, sigma
+      const float4 c = s[2];  // r, g, b, support
+      s_a[threadIdx.x] = make_float4((float)(m.x - ox), (float)(m.y - oy), q.x, q.y);
+      s_b[threadIdx.x] = make_float4(q.z, log2f(q.w), c.w, c.x);
+      s_c[threadIdx.x] = make_float2(c.y, c.z);
+    }
+    __syncthreads();
+    const int cnt = min(NT, rg.y - base);
+    if (!done) {
+      for (int j = 0; j < cnt; ++j) {
+        const float4 ga = s_a[j];
+        const float4 gb = s_b[j];
+        const float dx = fx - ga.x, dy = fy - ga.y;
+        const float u = fmaf(ga.z, dx, ga.w * dy);  // (Q d)_x
+        const float v = fmaf(ga.w, dx, gb.x * dy);  // (Q d)_y
+        const float q = fmaf(dx, u, dy * v);        // d^T Q d
+        if (q > gb.z) continue;                     // alpha < alpha_min
+        const float2 gc = s_c[j];
+        float alpha = exp2f(fmaf(q, -kHalfLog2e, gb.y));
+        const bool clamp = alpha > p.alpha_max;
+        alpha = clamp ? p.alpha_max : alpha;
+        const float w = T * alpha;
+        if (GRAD) {
+          const float ax = clamp ? 0.f : -alpha * u;
+          const float ay = clamp ? 0.f : -alpha * v;
+          const float axy = clamp ? 0.f : alpha * fmaf(u, v, -ga.w);
+          const float kx = fmaf(T, ax, Tx * alpha);
+          const float ky = fmaf(T, ay, Ty * alpha);
+          const float kxy = fmaf(T, axy, fmaf(Tx, ay, fmaf(Ty, ax, Txy * alpha)));
+          Bx0 = fmaf(gb.w, kx, Bx0);
+          Bx1 = fmaf(gc.x, kx, Bx1);
+          Bx2 = fmaf(gc.y, kx, Bx2);
+          By0 = fmaf(gb.w, ky, By0);
+          By1 = fmaf(gc.x, ky, By1);
+          By2 = fmaf(gc.y, ky, By2);
+          Bxy0 = fmaf(gb.w, kxy, Bxy0);
+          Bxy1 = fmaf(gc.x, kxy, Bxy1);
+          Bxy2 = fmaf(gc.y, kxy, Bxy2);
+          Tx -= kx;
+          Ty -= ky;
+          Txy -= kxy;
+        }
+        B0 = fmaf(gb.w, w, B0);
+        B1 = fmaf(gc.x, w, B1);
+        B2 = fmaf(gc.y, w, B2);
+        T -= w;
+        ++nb;
+        if (T < p.t_min) {
+          done = true;
+          break;
+        }
+      }
+    }
+  }
+  if (!inside) return;
+  const int64_t pix = (int64_t)py * p.width + px;
+  if (GRAD) {
+    float4* o = reinterpret_cast<float4*>(out + pix * 12);
+    o[0] = make_float4(fmaf(T, p.bg[0], B0), fmaf(T, p.bg[1], B1), fmaf(T, p.bg[2], B2),
+                       fmaf(Tx, p.bg[0], Bx0));
+    o[1] = make_float4(fmaf(Tx, p.bg[1], Bx1), fmaf(Tx, p.bg[2], Bx2), fmaf(Ty, p.bg[0], By0),
+                       fmaf(Ty, p.bg[1], By1));
+    o[2] = make_float4(fmaf(Ty, p.bg[2], By2), fmaf(Txy, p.bg[0], Bxy0),
+                       fmaf(Txy, p.bg[1], Bxy1), fmaf(Txy, p.bg[2], Bxy2));
+  } else {
+    float* o = out + pix * 3;
+    o[0] = fmaf(T, p.bg[0], B0);
+    o[1] = fmaf(T, p.bg[1], B1);
+    o[2] = fmaf(T, p.bg[2], B2);
+  }
+  if (n_blend) n_blend[pix] = nb;
+}
+
+template <int TILE, bool GRAD>
+void launch(const RasterParams& p, const gs_splat* splats, const int32_t* ids, const int2* ranges,
+            float* out, int32_t* n_blend, hipStream_t stream) {
+  const int64_t grid = xcd_grid(p.tiles);
+  raster_kernel<TILE, GRAD><<<(unsigned)grid, TILE * TILE, 0, stream>>>(p, splats, ids, ranges,
+                                                                       out, n_blend);
+}
+
+}  // namespace
+
+hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
+                         const int32_t* tile_ranges, const gs_camera& cam,
+                         const gs_raster_cfg& cfg, bool grads, float* out, int32_t* n_blend,
+                         hipStream_t stream) {
+  RasterParams p;
+  p.width = cam.width;
+  p.height = cam.height;
+  p.tiles_x = (int32_t)ceil_div(cam.width, cfg.tile_size);
+  p.tiles = (int64_t)p.tiles_x * ceil_div(cam.height, cfg.tile_size);
+  p.alpha_max = cfg.alpha_max;
+  p.t_min = cfg.t_min;
+  for (int k = 0; k < 3; ++k) p.bg[k] = cfg.bg[k];
+  const int2* r2 = reinterpret_cast<const int2*>(tile_ranges);
+  if (cfg.tile_size == 8) {
+    if (grads) launch<8, true>(p, splats, sorted_ids, r2, out, n_blend, stream);
+    else launch<8, false>(p, splats, sorted_ids, r2, out, n_blend, stream);
+  } else {
+    if (grads) launch<16, true>(p, splats, sorted_ids, r2, out, n_blend, stream);
+    else launch<16, false>(p, splats, sorted_ids, r2, out, n_blend, stream);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsup

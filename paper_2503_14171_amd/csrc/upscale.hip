@@ -1,0 +1,122 @@
+// gs_upscale_hermite: bicubic Hermite upscaling from image values and
+// analytical derivatives.
+//
+// Sec. "Image Gradient Based Upscaling" and Suppl. "Spline Image
+// Interpolation" of arXiv 2503.14171: each low-res cell gets the bicubic
+// p(x,y) = [1 x x^2 x^3] A [1 y y^2 y^3]^T with F = C A C^T, F holding the
+// values and the x, y, xy derivatives at the cell's four corners.  Written in
+// the cubic Hermite basis h(t) = C^-T [1 t t^2 t^3]^T,
+//     h0 = 2t^3 - 3t^2 + 1, h1 = -2t^3 + 3t^2, h2 = t^3 - 2t^2 + t, h3 = t^3 - t^2,
+// the patch is p(x,y) = h(x)^T F h(y), which separates: on a low-res row r
+//     V_r(x) = h0 f(i,r) + h1 f(i+1,r) + h2 f_x(i,r) + h3 f_x(i+1,r)
+//     D_r(x) = h0 f_y(i,r) + h1 f_y(i+1,r) + h2 f_xy(i,r) + h3 f_xy(i+1,r)
+// and p = h0(y) V_j + h1(y) V_j+1 + h2(y) D_j + h3(y) D_j+1.
+//
+// The kernel is HBM-bound (48 B read per low-res pixel, 12 B written per
+// high-res pixel).  One lane owns one output column and walks a band of
+// output rows; V and D of a low-res row are computed once per lane and reused
+// for every output row of the cell and for the next cell (which shares the
+// row), so a lane reads each low-res row once and spends 12 FMAs per output
+// pixel plus 24 per low-res row.  A wave stores 64 consecutive 12-byte pixels
+// (768 contiguous bytes) per output row.
+#include "gsup_internal.h"
+
+namespace gsup {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+__device__ __forceinline__ void hermite(float t, float& h0, float& h1, float& h2, float& h3) {
+  const float t2 = t * t;
+  h1 = t2 * fmaf(-2.f, t, 3.f);
+  h0 = 1.f - h1;
+  h2 = t * fmaf(t, t - 2.f, 1.f);
+  h3 = t2 * (t - 1.f);
+}
+
+// Cell index and local coordinate of output index X on an axis of n_lo -> n_hi:
+// u = (X + 1/2) n_lo / n_hi - 1/2 = ((2X+1) n_lo - n_hi) / (2 n_hi), computed
+// exactly in integers; the local coordinate is rounded once.
+__device__ __forceinline__ void axis_map(int X, int n_lo, int n_hi, int& cell, float& t) {
+  const int64_t num = (int64_t)(2 * X + 1) * n_lo - n_hi;
+  const int64_t den = 2 * (int64_t)n_hi;
+  int64_t i = floor_div(num, den);
+  i = i < 0 ? 0 : (i > n_lo - 2 ? n_lo - 2 : i);
+  cell = (int)i;
+  t = (float)(num - i * den) / (float)den;
+}
+
+// V (values) and D (y-derivatives) of low-res row r along x at the lane's column.
+__device__ __forceinline__ void row_terms(const float* __restrict__ in, int w, int r, int i, float h0,
+                                          float h1, float h2, float h3, float (&V)[3],
+                                          float (&D)[3]) {
+  const float4* a = reinterpret_cast<const float4*>(in + ((int64_t)r * w + i) * 12);
+  const float4 a0 = a[0], a1 = a[1], a2 = a[2];  // node i:   f rgb, fx r | fx gb, fy rg | fy b, fxy rgb
+  const float4 b0 = a[3], b1 = a[4], b2 = a[5];  // node i+1
+  V[0] = fmaf(h0, a0.x, fmaf(h1, b0.x, fmaf(h2, a0.w, h3 * b0.w)));
+  V[1] = fmaf(h0, a0.y, fmaf(h1, b0.y, fmaf(h2, a1.x, h3 * b1.x)));
+  V[2] = fmaf(h0, a0.z, fmaf(h1, b0.z, fmaf(h2, a1.y, h3 * b1.y)));
+  D[0] = fmaf(h0, a1.z, fmaf(h1, b1.z, fmaf(h2, a2.y, h3 * b2.y)));
+  D[1] = fmaf(h0, a1.w, fmaf(h1, b1.w, fmaf(h2, a2.z, h3 * b2.z)));
+  D[2] = fmaf(h0, a2.x, fmaf(h1, b2.x, fmaf(h2, a2.w, h3 * b2.w)));
+}
+
+template <int ROWS>
+__global__ __launch_bounds__(kThreads) void upscale_kernel(const float* __restrict__ in, int w,
+                                                           int h, float* __restrict__ out, int W,
+                                                           int H) {
+  const int X = blockIdx.x * kThreads + threadIdx.x;
+  if (X >= W) return;
+  const int Y0 = blockIdx.y * ROWS;
+  const int Y1 = min(Y0 + ROWS, H);
+  int i;
+  float tx;
+  axis_map(X, w, W, i, tx);
+  float hx0, hx1, hx2, hx3;
+  hermite(tx, hx0, hx1, hx2, hx3);
+
+  float V0[3], D0[3], V1[3], D1[3];
+  int jcur = -2;
+  float* o = out + ((int64_t)Y0 * W + X) * 3;
+  for (int Y = Y0; Y < Y1; ++Y, o += (int64_t)W * 3) {
+    int j;
+    float ty;
+    axis_map(Y, h, H, j, ty);
+    if (j != jcur) {
+      if (j == jcur + 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          V0[c] = V1[c];
+          D0[c] = D1[c];
+        }
+      } else {
+        row_terms(in, w, j, i, hx0, hx1, hx2, hx3, V0, D0);
+      }
+      row_terms(in, w, j + 1, i, hx0, hx1, hx2, hx3, V1, D1);
+      jcur = j;
+    }
+    float hy0, hy1, hy2, hy3;
+    hermite(ty, hy0, hy1, hy2, hy3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      o[c] = fmaf(hy0, V0[c], fmaf(hy1, V1[c], fmaf(hy2, D0[c], hy3 * D1[c])));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_upscale(const float* in, int32_t w, int32_t h, float* out, int32_t W, int32_t H,
+                          hipStream_t stream) {
+  constexpr int kRows = 16;
+  const dim3 grid((unsigned)ceil_div(W, kThreads), (unsigned)ceil_div(H, kRows));
+  upscale_kernel<kRows><<<grid, kThreads, 0, stream>>>(in, w, h, out, W, H);
+  return hipGetLastError();
+}
+
+}  // namespace gsup

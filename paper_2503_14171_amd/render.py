@@ -1,0 +1,98 @@
+"""Per-view pipeline over the C ABI: project -> bin/sort -> raster -> upscale.
+
+:class:`Renderer` keeps one scene's parameters and the per-view buffers in
+device memory and chains the four entry points on the current stream.  It
+only allocates buffers and forwards them; every step runs in libgsup's HIP
+kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class Renderer:
+    def __init__(self, scene: dict, device: str = "cuda"):
+        t = lambda k: torch.as_tensor(np.ascontiguousarray(scene[k]), dtype=torch.float32, device=device).contiguous()
+        self.means, self.log_scales, self.quats = t("means"), t("log_scales"), t("quats")
+        self.opacity = t("opacity")
+        self.sh = t("sh")
+        self.n = self.means.shape[0]
+        self.sh_degree = int(scene.get("sh_degree", round(self.sh.shape[1] ** 0.5) - 1))
+        self.device = device
+        self._bufs: dict = {}
+
+    # -- buffers -------------------------------------------------------------
+    def _view_bufs(self, cam: dict, cfg: dict):
+        key = (cam["width"], cam["height"], cfg["tile_size"])
+        b = self._bufs.get(key)
+        if b is None:
+            dev = self.device
+            n = max(self.n, 1)
+            tiles = L.gs_num_tiles(cam["width"], cam["height"], cfg["tile_size"])
+            b = dict(splats=torch.empty((n, L.SPLAT_FLOATS), dtype=torch.float32, device=dev),
+                     depth=torch.empty(n, dtype=torch.float32, device=dev),
+                     rect=torch.empty((n, 4), dtype=torch.int32, device=dev),
+                     ranges=torch.empty((tiles, 2), dtype=torch.int32, device=dev),
+                     capacity=0)
+            self._bufs[key] = b
+        return b
+
+    def _ensure_capacity(self, b: dict, cam: dict, cfg: dict, capacity: int):
+        if capacity <= b["capacity"]:
+            return
+        capacity = int(capacity)
+        b["ids"] = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+        ws = L.gs_bin_sort_workspace_size(self.n, capacity, cam, cfg)
+        b["workspace"] = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        b["capacity"] = capacity
+
+    # -- steps ---------------------------------------------------------------
+    def project(self, cam: dict, cfg: dict):
+        b = self._view_bufs(cam, cfg)
+        L.gs_project(self.means, self.log_scales, self.quats, self.opacity, self.sh, cam, cfg,
+                     b["splats"], b["depth"], b["rect"])
+        return b
+
+    def bin_sort(self, cam: dict, cfg: dict, b: dict | None = None) -> int:
+        b = b or self._view_bufs(cam, cfg)
+        if b["capacity"] == 0:
+            self._ensure_capacity(b, cam, cfg, 4 * self.n + 1024)
+        try:
+            k = L.gs_bin_sort(self.n, b["depth"], b["rect"], cam, cfg, b["capacity"], b["ids"],
+                              b["ranges"], b["workspace"])
+        except L.GsError as e:
+            if e.status != L.GS_ERR_CAPACITY or e.n_pairs is None or e.n_pairs >= 2 ** 31:
+                raise
+            self._ensure_capacity(b, cam, cfg, int(e.n_pairs * 1.25) + 1024)
+            k = L.gs_bin_sort(self.n, b["depth"], b["rect"], cam, cfg, b["capacity"], b["ids"],
+                              b["ranges"], b["workspace"])
+        b["n_pairs"] = k
+        return k
+
+    def raster(self, cam: dict, cfg: dict, want_grads: bool = True, out=None, n_blend=None, b=None):
+        b = b or self._view_bufs(cam, cfg)
+        C = 12 if want_grads else 3
+        if out is None:
+            out = torch.empty((cam["height"], cam["width"], C), dtype=torch.float32, device=self.device)
+        L.gs_raster_grad(b["splats"], b["ids"], b["ranges"], cam, cfg, want_grads, out, n_blend)
+        return out
+
+    def render(self, cam: dict, cfg: dict, want_grads: bool = True, out=None, n_blend=None):
+        """Low-res colour [H, W, 12] with derivatives (or [H, W, 3] plain)."""
+        b = self.project(cam, cfg)
+        self.bin_sort(cam, cfg, b)
+        return self.raster(cam, cfg, want_grads, out, n_blend, b)
+
+    @staticmethod
+    def upscale(lowres: torch.Tensor, W: int, H: int, out=None):
+        if out is None:
+            out = torch.empty((H, W, 3), dtype=torch.float32, device=lowres.device)
+        L.gs_upscale_hermite(lowres, out)
+        return out
+
+    def render_upscaled(self, cam: dict, cfg: dict, W: int, H: int, lowres=None, out=None):
+        low = self.render(cam, cfg, True, lowres)
+        return self.upscale(low, W, H, out), low

@@ -1,0 +1,289 @@
+"""GPU parity of each stage against the FP64 oracle, fed identical inputs.
+
+Each stage is given inputs computed by the oracle (never by another HIP
+stage), so a mismatch points at the kernel under test:
+  gs_project          vs oracle projection (same FP32 scene)
+  gs_bin_sort         vs a plain lexicographic sort of the oracle's rects/depths
+  gs_raster_grad      vs oracle compositing of the same FP32-rounded splats
+  gs_upscale_hermite  vs oracle patches of the same FP32 low-res buffer
+"""
+import numpy as np
+import pytest
+
+from parity_util import (TOL, assert_within, best_variant_error, report, rounded_proj,
+                         splat_records, summarize)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2503_14171_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+# ---------------------------------------------------------------------------
+# gs_project
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["tiny", "tiny_deg3_orbit", "clusters_subset"])
+def test_project_matches_oracle(gs, oracle, case):
+    import torch
+    from paper_2503_14171_amd import scenes
+    if case == "tiny":
+        sc = scenes.workload_scene("tiny")
+        cam = scenes.workload_camera("tiny")
+    elif case == "tiny_deg3_orbit":
+        sc = scenes.make_scene("uniform", 20000, 21, 3)
+        sc["means"] *= np.float32(2.2)  # near-plane culls and J clamps
+        cam = scenes.orbit_camera(200, 120, 40.0, -15.0)
+    else:
+        sc = scenes.make_scene("clusters", 100000, 22, 3)
+        cam = scenes.make_camera(960, 540)
+    for tile in (8, 16):
+        cfg = scenes.render_config(sc["sh_degree"], tile_size=tile)
+        print(f"project case={case} tile={tile} n={sc['means'].shape[0]}", flush=True)
+        pr = oracle.project(sc, cam, cfg)
+        n = sc["means"].shape[0]
+        splats = torch.zeros((n, 12), dtype=torch.float32, device="cuda")
+        depth = torch.zeros(n, dtype=torch.float32, device="cuda")
+        rect = torch.zeros((n, 4), dtype=torch.int32, device="cuda")
+        gs.gs_project(_dev(sc["means"]), _dev(sc["log_scales"]), _dev(sc["quats"]),
+                      _dev(sc["opacity"]), _dev(sc["sh"]), cam, cfg, splats, depth, rect)
+        torch.cuda.synchronize()
+        s = splats.cpu().numpy()
+        d = depth.cpu().numpy()
+        r = rect.cpu().numpy()
+        ref_rect = oracle.tile_rects(pr, cam["width"], cam["height"], tile)
+        np.testing.assert_array_equal(r, ref_rect)
+        live = ref_rect[:, 2] > ref_rect[:, 0]
+        assert live.sum() > 0.3 * n
+        # the sort key is bit-identical: camera z rounded to FP32
+        np.testing.assert_array_equal(d[live], pr["depth"][live].astype(np.float32))
+        mean = s.view(np.float64)[:, 0:2]
+        np.testing.assert_allclose(mean[live], pr["mean2d"][live], rtol=0, atol=1e-9)
+        np.testing.assert_allclose(s[live, 4:7], pr["conic"][live], rtol=2e-7, atol=1e-12)
+        np.testing.assert_array_equal(s[live, 7], sc["opacity"][live])
+        np.testing.assert_allclose(s[live, 8:11], pr["rgb"][live], rtol=0, atol=2e-7)
+        amin = float(np.float32(cfg["alpha_min"]))
+        np.testing.assert_allclose(s[live, 11], 2 * np.log(pr["opacity"][live] / amin), rtol=2e-7)
+        # culled Gaussians: no tiles, zeroed record, infinite depth
+        culled = ~pr["valid"]
+        assert np.all(r[culled] == 0) and np.all(s[culled] == 0) and np.all(np.isinf(d[culled]))
+
+
+# ---------------------------------------------------------------------------
+# gs_bin_sort
+# ---------------------------------------------------------------------------
+def _run_bin_sort(gs, depth32, rect, cam, cfg, capacity=None):
+    import torch
+    n = depth32.shape[0]
+    tiles = gs.gs_num_tiles(cam["width"], cam["height"], cfg["tile_size"])
+    cnt = np.maximum(rect[:, 2] - rect[:, 0], 0) * np.maximum(rect[:, 3] - rect[:, 1], 0)
+    K = int(cnt.sum())
+    cap = K if capacity is None else capacity
+    ws = torch.empty(gs.gs_bin_sort_workspace_size(n, cap, cam, cfg), dtype=torch.uint8, device="cuda")
+    ids = torch.full((max(cap, 1),), -7, dtype=torch.int32, device="cuda")
+    ranges = torch.full((tiles, 2), -7, dtype=torch.int32, device="cuda")
+    k = gs.gs_bin_sort(n, _dev(depth32), _dev(rect), cam, cfg, cap, ids, ranges, ws)
+    torch.cuda.synchronize()
+    assert k == K
+    return ids.cpu().numpy()[:K], ranges.cpu().numpy()
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_bin_sort_matches_lexsort_oracle_scene(gs, oracle, tile):
+    from paper_2503_14171_amd import scenes
+    sc = scenes.make_scene("clusters", 60000, 23, 0)
+    cam = scenes.make_camera(640, 360)
+    cfg = scenes.render_config(0, tile_size=tile)
+    pr = oracle.project(sc, cam, cfg)
+    rect = oracle.tile_rects(pr, 640, 360, tile)
+    d32 = np.where(pr["valid"], pr["depth"], np.inf).astype(np.float32)
+    print(f"bin_sort scene tile={tile}", flush=True)
+    ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
+    ref_ids, ref_ranges = oracle.tile_lists(d32, rect, *_tiles_xy(cam, tile))
+    np.testing.assert_array_equal(ranges, ref_ranges)
+    np.testing.assert_array_equal(ids, ref_ids)
+
+
+def _tiles_xy(cam, tile):
+    return -(-cam["width"] // tile), -(-cam["height"] // tile)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_bin_sort_stable_under_depth_ties(gs, oracle, seed):
+    """Few distinct depths: equal keys must keep index order; many pairs so
+    the sort runs several blocks and a two-level scan."""
+    from paper_2503_14171_amd import scenes
+    rng = np.random.default_rng(seed)
+    n = 200000
+    cam = scenes.make_camera(1024, 768)
+    cfg = scenes.render_config(0, tile_size=16)
+    tx, ty = _tiles_xy(cam, 16)
+    x0 = rng.integers(0, tx, n)
+    y0 = rng.integers(0, ty, n)
+    w = rng.integers(0, 4, n)
+    h = rng.integers(1, 4, n)
+    rect = np.stack([x0, y0, np.minimum(x0 + w, tx), np.minimum(y0 + h, ty)], 1).astype(np.int32)
+    d32 = rng.choice(np.array([0.5, 1.0, 1.0000001, 3.25, 7.0], np.float32), n)
+    print(f"bin_sort ties seed={seed}", flush=True)
+    ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
+    ref_ids, ref_ranges = oracle.tile_lists(d32, rect, tx, ty)
+    assert ids.shape[0] > 65536 * 2
+    np.testing.assert_array_equal(ranges, ref_ranges)
+    np.testing.assert_array_equal(ids, ref_ids)
+
+
+def test_bin_sort_capacity_error_and_empty(gs, oracle):
+    import torch
+    from paper_2503_14171_amd import scenes
+    cam = scenes.make_camera(64, 48)
+    cfg = scenes.render_config(0, tile_size=8)
+    rect = np.array([[0, 0, 2, 2], [1, 1, 3, 2], [0, 0, 0, 0]], np.int32)
+    d32 = np.array([2.0, 1.0, 3.0], np.float32)
+    print("bin_sort capacity", flush=True)
+    with pytest.raises(gs.GsError) as ei:
+        _run_bin_sort(gs, d32, rect, cam, cfg, capacity=3)
+    assert ei.value.status == gs.GS_ERR_CAPACITY and ei.value.n_pairs == 6
+    ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
+    ref_ids, ref_ranges = oracle.tile_lists(d32, rect, 8, 6)
+    np.testing.assert_array_equal(ids, ref_ids)
+    np.testing.assert_array_equal(ranges, ref_ranges)
+    # no pairs at all: every range empty
+    ids, ranges = _run_bin_sort(gs, d32, np.zeros((3, 4), np.int32), cam, cfg)
+    assert ids.size == 0 and np.all(ranges == 0)
+    # n == 0
+    ws = torch.empty(gs.gs_bin_sort_workspace_size(0, 0, cam, cfg), dtype=torch.uint8, device="cuda")
+    rg = torch.full((48, 2), -1, dtype=torch.int32, device="cuda")
+    ids0 = torch.empty(1, dtype=torch.int32, device="cuda")
+    k = gs.gs_bin_sort(0, torch.empty(0, device="cuda"), torch.empty((0, 4), dtype=torch.int32, device="cuda"),
+                       cam, cfg, 0, ids0, rg, ws)
+    torch.cuda.synchronize()
+    assert k == 0 and torch.all(rg == 0)
+
+
+# ---------------------------------------------------------------------------
+# gs_raster_grad (fed the oracle's splats and tile lists)
+# ---------------------------------------------------------------------------
+def _raster_stage(gs, oracle, sc, cam, cfg, want_grads=True, sample=None, seed=0):
+    import torch
+    pr = oracle.project(sc, cam, cfg)
+    rec = splat_records(pr, cfg)
+    rp = rounded_proj(pr)
+    tile = cfg["tile_size"]
+    rect = oracle.tile_rects(pr, cam["width"], cam["height"], tile)
+    d32 = np.where(pr["valid"], pr["depth"], np.inf).astype(np.float32)
+    ids, ranges = oracle.tile_lists(d32, rect, *_tiles_xy(cam, tile))
+    H, W = cam["height"], cam["width"]
+    C = 12 if want_grads else 3
+    out = torch.full((H, W, C), np.nan, dtype=torch.float32, device="cuda")
+    nbl = torch.full((H, W), -1, dtype=torch.int32, device="cuda")
+    gs.gs_raster_grad(_dev(rec), _dev(ids if ids.size else np.zeros(1, np.int32)), _dev(ranges), cam,
+                      cfg, want_grads, out, nbl)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().reshape(-1, C)
+    nb = nbl.cpu().numpy().reshape(-1)
+    yy, xx = np.meshgrid(np.arange(H, dtype=float), np.arange(W, dtype=float), indexing="ij")
+    px, py = xx.reshape(-1), yy.reshape(-1)
+    idx = np.arange(H * W)
+    if sample is not None and sample < H * W:
+        idx = np.random.default_rng(seed).choice(H * W, sample, replace=False)
+    order = oracle.depth_order(rp)
+    ref = oracle.composite(rp, order, cfg, px[idx], py[idx], variants=True)
+    return g[idx], nb[idx], ref
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("want_grads", [True, False])
+def test_raster_stage_tiny(gs, oracle, tile, want_grads):
+    from paper_2503_14171_amd import scenes
+    sc = scenes.workload_scene("tiny")
+    cam = scenes.workload_camera("tiny")
+    cfg = scenes.render_config(0, tile_size=tile)
+    print(f"raster stage tiny tile={tile} grads={want_grads}", flush=True)
+    g, nb, ref = _raster_stage(gs, oracle, sc, cam, cfg, want_grads)
+    err, masked = best_variant_error(g, ref)
+    report(f"raster_stage_tiny_t{tile}_g{int(want_grads)}", summarize(err, masked, ref["out"]))
+    assert_within(err, masked)
+    clean = ref["n_amb"] == 0
+    np.testing.assert_array_equal(nb[clean], ref["n_blend"][clean])
+
+
+def test_raster_stage_ragged_bg_opaque(gs, oracle):
+    """Image size not a multiple of the tile, non-zero background, opaque
+    splats (alpha clamp and early termination everywhere)."""
+    from paper_2503_14171_amd import scenes
+    sc = scenes.make_scene("uniform", 6000, 24, 0)
+    sc["opacity"][::2] = np.float32(0.999)
+    cam = scenes.make_camera(101, 75)
+    cfg = scenes.render_config(0, tile_size=16, bg=(0.25, 0.5, 1.0))
+    print("raster stage ragged", flush=True)
+    g, nb, ref = _raster_stage(gs, oracle, sc, cam, cfg, True)
+    err, masked = best_variant_error(g, ref)
+    report("raster_stage_ragged", summarize(err, masked, ref["out"]))
+    assert_within(err, masked)
+
+
+def test_raster_stage_clusters_sampled(gs, oracle):
+    from paper_2503_14171_amd import scenes
+    sc = scenes.make_scene("clusters", 100000, 25, 3)
+    cam = scenes.make_camera(480, 270)
+    cfg = scenes.render_config(3, tile_size=16)
+    print("raster stage clusters sampled", flush=True)
+    g, nb, ref = _raster_stage(gs, oracle, sc, cam, cfg, True, sample=3000)
+    err, masked = best_variant_error(g, ref)
+    report("raster_stage_clusters", summarize(err, masked, ref["out"]))
+    assert_within(err, masked)
+
+
+# ---------------------------------------------------------------------------
+# gs_upscale_hermite (fed an oracle-rendered low-res buffer)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def tiny_lowres(oracle):
+    from paper_2503_14171_amd import scenes
+    sc = scenes.workload_scene("tiny")
+    r = oracle.render(sc, scenes.workload_camera("tiny"), scenes.render_config(0))
+    return r["img"].astype(np.float32)
+
+
+@pytest.mark.parametrize("W,H", [(256, 256), (128, 128), (384, 384), (512, 512), (300, 211),
+                                 (129, 400), (1000, 129)])
+def test_upscale_stage(gs, oracle, tiny_lowres, W, H):
+    import torch
+    low = tiny_lowres
+    out = torch.full((H, W, 3), np.nan, dtype=torch.float32, device="cuda")
+    print(f"upscale stage {W}x{H}", flush=True)
+    gs.gs_upscale_hermite(_dev(low), out)
+    torch.cuda.synchronize()
+    ref = oracle.upscale(low.astype(np.float64), W, H)
+    err = np.abs(out.cpu().numpy() - ref).reshape(-1, 3)
+    report(f"upscale_stage_{W}x{H}", summarize(err, np.zeros(err.shape[0], bool)))
+    assert err.max() < 5e-6
+
+
+def test_upscale_stage_small_and_identity(gs, oracle):
+    import torch
+    rng = np.random.default_rng(3)
+    for (w, h, W, H) in [(2, 2, 2, 2), (2, 2, 7, 5), (3, 5, 3, 5), (17, 9, 51, 27), (5, 4, 640, 4)]:
+        low = rng.standard_normal((h, w, 12)).astype(np.float32)
+        out = torch.full((H, W, 3), np.nan, dtype=torch.float32, device="cuda")
+        print(f"upscale small {w}x{h}->{W}x{H}", flush=True)
+        gs.gs_upscale_hermite(_dev(low), out)
+        torch.cuda.synchronize()
+        ref = oracle.upscale(low.astype(np.float64), W, H)
+        np.testing.assert_allclose(out.cpu().numpy(), ref, atol=2e-5, rtol=0)
+        if (w, h) == (W, H):
+            np.testing.assert_allclose(out.cpu().numpy(), low[..., :3], atol=1e-6)
