@@ -124,7 +124,8 @@ size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* 
  *   sorted_ids [capacity] int32  (device) splat indices; tile t's list is
  *                               sorted_ids[tile_ranges[2t] .. tile_ranges[2t+1]),
  *                               ordered by (FP32 depth, index)
- *   tile_ranges [T,2] int32     (device) [start, end) per tile, T = gs_num_tiles(..)
+ *   tile_ranges [T,2] int32     (device) [start, end) per tile, T = gs_num_tiles(..);
+ *                               [0, 0) for a tile no splat reaches
  *   n_pairs                     (HOST) number of (tile, splat) pairs K
  * workspace: device scratch of at least gs_bin_sort_workspace_size(n, capacity, ..)
  * bytes, 256-byte aligned; its contents are undefined after the call.

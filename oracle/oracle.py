@@ -277,7 +277,8 @@ def tile_lists(depth32: np.ndarray, rect: np.ndarray, tiles_x: int, tiles_y: int
     """Per-tile Gaussian lists in (FP32 depth, index) order.
 
     Returns (ids, ranges): ids is the concatenation of all tile lists in tile
-    order (tile = ty * tiles_x + tx), ranges [T, 2] the [start, end) of each."""
+    order (tile = ty * tiles_x + tx), ranges [T, 2] the [start, end) of each
+    ([0, 0) for an empty tile)."""
     n = rect.shape[0]
     cnt = np.maximum(rect[:, 2] - rect[:, 0], 0) * np.maximum(rect[:, 3] - rect[:, 1], 0)
     gid = np.repeat(np.arange(n, dtype=np.int64), cnt)
@@ -293,4 +294,5 @@ def tile_lists(depth32: np.ndarray, rect: np.ndarray, tiles_x: int, tiles_y: int
     counts = np.bincount(tile, minlength=T)
     starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
     ranges = np.stack([starts, starts + counts], 1)
+    ranges[counts == 0] = 0  # an empty tile's range is [0, 0)
     return gid[o].astype(np.int32), ranges.astype(np.int32)
