@@ -1,0 +1,260 @@
+"""Benchmark of the gradient-aware upscaling hot path on one MI355X.
+
+A step is one pass of the whole path over one camera view of a synthetic
+scene whose inputs already sit in HBM: gs_project -> gs_bin_sort ->
+gs_raster_grad (colour + dI/dx, dI/dy, d2I/dxdy) -> gs_upscale_hermite.
+The default workload is the 3M-Gaussian scene (SH degree 3) rendered at
+960x540 and upscaled x4 to 3840x2160.  Throughput is high-res output
+megapixels per second.
+
+Beside it the script measures, on the same GPU, the direct full-resolution
+render (gs_project + gs_bin_sort + plain gs_raster_grad at 3840x2160), the
+PSNR of the upscaled image against it, per-kernel HIP-event times, the
+raster kernel's arithmetic roofline and the upscaler's HBM roofline, and the
+FP64 CPU oracle on a bounded sample of the same frame (rank 0, N = 1).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene_x4]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np
+
+METRIC = "upscaled output Mpix/s vs direct full-res raster (same GPU) at PSNR gap; BW %"
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP32_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), no packed FP32
+# FP32 operations of the method per blended fragment (FMA = 2), grad and plain
+FLOP_PER_BLEND = {True: 64, False: 25}
+# Bytes the upscaler must move: 48 per low-res pixel read, 12 per output pixel written
+UPSCALE_BYTES_LO, UPSCALE_BYTES_HI = 48, 12
+
+WORKLOADS = {
+    "scene_x4": ("scene", 4), "scene_x3": ("scene", 3), "scene_x2": ("scene", 2),
+    "clusters_x2": ("clusters", 2), "tiny_x2": ("tiny", 2),
+}
+
+
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def run_gpu(args):
+    import torch
+
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.render import Renderer
+
+    name, s = WORKLOADS[args.workload]
+    sc = scenes.workload_scene(name)
+    cam = scenes.workload_camera(name)
+    cfg = scenes.render_config(sc["sh_degree"], tile_size=args.tile)
+    w, h = cam["width"], cam["height"]
+    W, H = w * s, h * s
+    cam_hi = scenes.scale_camera(cam, W, H)
+    torch.cuda.set_device(0)
+    rd = Renderer(sc)
+
+    # Rotating output sets (> 512 MB in total) so that the 256 MB MALL does
+    # not absorb the upscaler's reads and writes between steps.
+    set_bytes = (w * h * 12 + W * H * 3) * 4
+    nsets = max(2, math.ceil(640e6 / set_bytes))
+    lows = [torch.empty((h, w, 12), dtype=torch.float32, device="cuda") for _ in range(nsets)]
+    ups = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(nsets)]
+
+    def step(k, ev=None):
+        lo, up = lows[k % nsets], ups[k % nsets]
+        if ev:
+            ev[0].record()
+        b = rd.project(cam, cfg)
+        if ev:
+            ev[1].record()
+        rd.bin_sort(cam, cfg, b)
+        if ev:
+            ev[2].record()
+        rd.raster(cam, cfg, True, lo, b=b)
+        if ev:
+            ev[3].record()
+        rd.upscale(lo, W, H, up)
+        if ev:
+            ev[4].record()
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    evs = [_events(torch, 5) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k, evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])
+    st_ms = stage.mean(0)
+
+    # direct full-resolution render (plain compositing) on the same GPU
+    direct_out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+
+    def direct_step(ev=None):
+        if ev:
+            ev[0].record()
+        b = rd.project(cam_hi, cfg)
+        if ev:
+            ev[1].record()
+        rd.bin_sort(cam_hi, cfg, b)
+        if ev:
+            ev[2].record()
+        rd.raster(cam_hi, cfg, False, direct_out, b=b)
+        if ev:
+            ev[3].record()
+
+    for _ in range(max(1, args.warmup)):
+        direct_step()
+    torch.cuda.synchronize()
+    devs = [_events(torch, 4) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        direct_step(devs[k])
+    torch.cuda.synchronize()
+    ms_direct = 1e3 * (time.perf_counter() - t0) / args.steps
+    dstage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in devs]).mean(0)
+
+    # quality of the upscaled frame against the direct render
+    up = ups[(args.warmup + args.steps - 1) % nsets].clamp(0, 1)
+    ref = direct_out.clamp(0, 1)
+    mse = torch.mean((up - ref) ** 2).item()
+    psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+
+    # algorithmic work of the raster launch: blended fragments (one extra,
+    # untimed launch with the per-pixel counter)
+    nbl = torch.empty((h, w), dtype=torch.int32, device="cuda")
+    rd.render(cam, cfg, True, lows[0], nbl)
+    frags = int(nbl.sum().item())
+    nbl_hi = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    rd.render(cam_hi, cfg, False, direct_out, nbl_hi)
+    frags_hi = int(nbl_hi.sum().item())
+    pairs = rd._bufs[(w, h, cfg["tile_size"])]["n_pairs"]
+    pairs_hi = rd._bufs[(W, H, cfg["tile_size"])]["n_pairs"]
+
+    ras_ms = st_ms[2]
+    achieved = frags * FLOP_PER_BLEND[True] / (ras_ms * 1e-3) / 1e12
+    up_bytes = w * h * UPSCALE_BYTES_LO + W * H * UPSCALE_BYTES_HI
+    up_gbs = up_bytes / (st_ms[3] * 1e-3) / 1e9
+    value = W * H / (ms_step * 1e-3) / 1e6
+    direct_value = W * H / (ms_direct * 1e-3) / 1e6
+    return dict(
+        name=name, s=s, w=w, h=h, W=W, H=H, n=rd.n, cfg=cfg, value=value, ms_step=ms_step,
+        stages_ms=dict(project=st_ms[0], bin_sort=st_ms[1], raster_grad=st_ms[2], upscale=st_ms[3]),
+        direct=dict(value=direct_value, ms_per_frame=ms_direct,
+                    stages_ms=dict(project=dstage[0], bin_sort=dstage[1], raster_plain=dstage[2]),
+                    pairs=pairs_hi, blended_fragments=frags_hi),
+        psnr=psnr, frags=frags, pairs=pairs, achieved_tflops=achieved, up_gbs=up_gbs,
+        up_bytes=up_bytes, scene=sc, cam=cam)
+
+
+def cpu_baseline(res, budget_s):
+    """The FP64 oracle on a bounded sample of the same frame: projection and
+    depth order of every Gaussian, compositing of a random sample of low-res
+    pixels, patches of a sample of output pixels; scaled to the whole frame."""
+    from oracle import oracle
+
+    sc, cam, cfg = res["scene"], res["cam"], res["cfg"]
+    w, h, W, H = res["w"], res["h"], res["W"], res["H"]
+    t0 = time.perf_counter()
+    proj = oracle.project(sc, cam, cfg)
+    order = oracle.depth_order(proj)
+    t_setup = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    npx, t_pix = 0, 0.0
+    chunk = 16
+    while t_pix < budget_s and npx < w * h:
+        xs = rng.integers(0, w, chunk)
+        ys = rng.integers(0, h, chunk)
+        t1 = time.perf_counter()
+        oracle.composite(proj, order, cfg, xs, ys)
+        t_pix += time.perf_counter() - t1
+        npx += chunk
+    img = rng.standard_normal((h, w, 12))
+    nup = 200000
+    X = rng.integers(0, W, nup).astype(np.int32)
+    Y = rng.integers(0, H, nup).astype(np.int32)
+    t1 = time.perf_counter()
+    oracle.upscale(img, W, H, X, Y)
+    t_up = time.perf_counter() - t1
+    t_frame = t_setup + t_pix * (w * h) / npx + t_up * (W * H) / nup
+    return dict(value=W * H / t_frame / 1e6, unit="Mpix/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"projection + depth order of all {res['n']} Gaussians ({t_setup:.1f} s), "
+                        f"{npx} random low-res pixels composited ({t_pix:.1f} s), {nup} output "
+                        f"pixels upscaled ({t_up:.1f} s); frame time extrapolated to "
+                        f"{w}x{h} -> {W}x{H} = {t_frame:.0f} s"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="scene_x4", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle compositing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    res = run_gpu(args)
+    name, s, w, h, W, H = (res[k] for k in ("name", "s", "w", "h", "W", "H"))
+    line = {
+        "metric": METRIC,
+        "value": round(res["value"], 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{name}: {res['n']} Gaussians, SH degree {res['cfg']['sh_degree']}, "
+                               f"{w}x{h} rendered with gradients, upscaled x{s} to {W}x{H}",
+                   "gaussians": res["n"], "lowres": [w, h], "highres": [W, H], "scale": s,
+                   "tile": args.tile},
+        "roofline": {"kernel": "gs_raster_grad", "bound": "alu",
+                     "achieved": round(res["achieved_tflops"], 3), "peak": FP32_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(res["achieved_tflops"] / FP32_VALU_TFLOPS, 4),
+                     "traffic": None,
+                     "units": f"{res['frags']} blended fragments x {FLOP_PER_BLEND[True]} FLOP"},
+        "upscaler_roofline": {"kernel": "gs_upscale_hermite", "bound": "hbm",
+                              "achieved": round(res["up_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(res["up_gbs"] / HBM_PEAK_GBS, 4),
+                              "bytes": res["up_bytes"], "traffic": None},
+        "stages_ms": {k: round(v, 4) for k, v in res["stages_ms"].items()},
+        "direct": {"value": round(res["direct"]["value"], 2), "unit": "Mpix/s",
+                   "ms_per_frame": round(res["direct"]["ms_per_frame"], 4),
+                   "stages_ms": {k: round(v, 4) for k, v in res["direct"]["stages_ms"].items()}},
+        "speedup_vs_direct": round(res["value"] / res["direct"]["value"], 3),
+        "psnr_vs_direct_db": round(res["psnr"], 2),
+        "pairs": {"lowres": res["pairs"], "direct": res["direct"]["pairs"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(res, args.cpu_budget)
+        line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 6)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

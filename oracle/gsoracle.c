@@ -541,3 +541,15 @@ void or_upscale(const double* img, int32_t w, int32_t h, int32_t W, int32_t H, i
 }
 
 int32_t or_max_variants(void) { return OR_MAX_VAR; }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Threads an OpenMP region of the oracle uses. */
+int32_t or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -79,6 +79,7 @@ def _load():
         lib.or_patch_eval.argtypes = [P, i32, i32, i64, P, P, P]
         lib.or_upscale.argtypes = [P, i32, i32, i32, i32, i64, P, P, P]
         lib.or_max_variants.restype = i32
+        lib.or_num_threads.restype = i32
         for f in ("or_sh_basis", "or_project", "or_composite", "or_hermite_matrices",
                   "or_patch_eval", "or_upscale"):
             getattr(lib, f).restype = None
@@ -197,6 +198,11 @@ def render(scene: dict, cam: dict, cfg: dict, variants: bool = False) -> dict:
         out["variants"] = r["variants"].reshape(H, W, -1, 12)
         out["n_var"] = r["n_var"].reshape(H, W)
     return out
+
+
+def num_threads() -> int:
+    """Host threads the oracle's parallel loops use."""
+    return int(_load().or_num_threads())
 
 
 def hermite_matrices():

@@ -88,3 +88,28 @@ def assert_within(err: np.ndarray, masked: np.ndarray, tol: float = TOL, max_mas
     if worst > tol:
         idx = np.unravel_index(np.argmax(np.where(ok[:, None], err, 0)), err.shape)
         raise AssertionError(f"max error {worst:.3e} > {tol:.1e} at point {idx[0]} channel {idx[1]}")
+
+
+def upscaled_candidates(oracle, corner_variants, u, v, max_combos=256):
+    """Every upscaled rgb the oracle accepts at one output pixel.
+
+    corner_variants: four arrays [k_c, 12] of valid results at the cell's
+    corners (0,0), (1,0), (0,1), (1,1); (u, v) the local patch coordinates.
+    Returns [n_combos, 3], or None when there are too many combinations."""
+    import itertools
+    sizes = [c.shape[0] for c in corner_variants]
+    if min(sizes) == 0 or int(np.prod(sizes)) > max_combos:
+        return None
+    out = []
+    for a, b, c, d in itertools.product(*[range(s) for s in sizes]):
+        img = np.stack([np.stack([corner_variants[0][a], corner_variants[1][b]]),
+                        np.stack([corner_variants[2][c], corner_variants[3][d]])])
+        out.append(oracle.patch_eval(img, [u], [v])[0, :3])
+    return np.array(out)
+
+
+def node_variants(ref: dict, p: int) -> np.ndarray:
+    """Valid results [k, 12] of oracle point p (k = 0 when unresolved)."""
+    if "variants" not in ref:
+        return ref["out"][p][None]
+    return ref["variants"][p, : ref["n_var"][p]]

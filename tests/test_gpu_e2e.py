@@ -12,7 +12,8 @@ mode bit for bit, runs are deterministic, tile sizes agree.
 import numpy as np
 import pytest
 
-from parity_util import assert_within, best_variant_error, report, summarize
+from parity_util import (assert_within, best_variant_error, node_variants, report, summarize,
+                         upscaled_candidates)
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +34,8 @@ def _oracle_nodes(oracle, proj, order, cfg, xs, ys):
 
 def _check_upscaled_samples(oracle, proj, order, cfg, low_wh, hi_wh, up_gpu, samples, seed):
     """Oracle upscaled value at sampled high-res pixels, from oracle-composited
-    corner nodes; samples whose nodes have near ties are left out (counted)."""
+    corner nodes.  Where a corner has near ties every combination of its valid
+    results is a valid upscaled value; the GPU must match one of them."""
     (w, h), (W, H) = low_wh, hi_wh
     rng = np.random.default_rng(seed)
     X = rng.integers(0, W, samples)
@@ -42,16 +44,19 @@ def _check_upscaled_samples(oracle, proj, order, cfg, low_wh, hi_wh, up_gpu, sam
     xs = np.concatenate([i, i + 1, i, i + 1])
     ys = np.concatenate([j, j, j + 1, j + 1])
     nodes = _oracle_nodes(oracle, proj, order, cfg, xs, ys)
-    amb = (nodes["n_amb"] > 0).reshape(4, samples).any(0)
-    v = nodes["out"].reshape(4, samples, 12)
     u = (X + 0.5) * w / W - 0.5 - i
     vv = (Y + 0.5) * h / H - 0.5 - j
-    ref = np.empty((samples, 3))
+    err = np.zeros((samples, 3))
+    masked = np.zeros(samples, bool)
     for s in range(samples):
-        img = np.stack([np.stack([v[0, s], v[1, s]]), np.stack([v[2, s], v[3, s]])])  # [2,2,12]
-        ref[s] = oracle.patch_eval(img, [u[s]], [vv[s]])[0, :3]
-    err = np.abs(up_gpu[Y, X] - ref)
-    return err, amb
+        corners = [node_variants(nodes, c * samples + s) for c in range(4)]
+        cand = upscaled_candidates(oracle, corners, u[s], vv[s])
+        if cand is None:
+            masked[s] = True
+            continue
+        e = np.abs(cand - up_gpu[Y[s], X[s]][None])
+        err[s] = e[np.argmin(e.max(1))]
+    return err, masked
 
 
 def test_e2e_tiny_all_pixels(torch_mod, oracle):
@@ -75,14 +80,25 @@ def test_e2e_tiny_all_pixels(torch_mod, oracle):
         err, masked = best_variant_error(g, ref_nodes)
         report(f"e2e_tiny_lowres_t{tile}", summarize(err, masked, ref_nodes["out"]))
         assert_within(err, masked)
-        # upscaled: pixels whose patch touches a near-tie node are left out
+        # upscaled: where a patch corner has near ties, any combination of the
+        # corners' valid results is a valid upscaled value
         u = up.cpu().numpy()
         Yg, Xg = np.meshgrid(np.arange(256), np.arange(256), indexing="ij")
         i, j = oracle.upscale_cell(Xg, Yg, 128, 128, 256, 256)
         touch = amb_nodes[j, i] | amb_nodes[j, i + 1] | amb_nodes[j + 1, i] | amb_nodes[j + 1, i + 1]
-        e_up = np.abs(u - ref_up).reshape(-1, 3)
-        report(f"e2e_tiny_upscaled_t{tile}", summarize(e_up, touch.reshape(-1)))
-        assert_within(e_up, touch.reshape(-1), max_masked_frac=5e-3)
+        e_up = np.abs(u - ref_up)
+        masked = np.zeros((256, 256), bool)
+        for (yy, xx) in zip(*np.nonzero(touch)):
+            ci, cj = i[yy, xx], j[yy, xx]
+            corners = [node_variants(ref_nodes, (cj + dy) * 128 + ci + dx) for dy, dx in ((0, 0), (0, 1), (1, 0), (1, 1))]
+            cand = upscaled_candidates(oracle, corners, (xx + 0.5) / 2 - 0.5 - ci, (yy + 0.5) / 2 - 0.5 - cj)
+            if cand is None:
+                masked[yy, xx] = True
+                continue
+            e = np.abs(cand - u[yy, xx][None])
+            e_up[yy, xx] = e[np.argmin(e.max(1))]
+        report(f"e2e_tiny_upscaled_t{tile}", summarize(e_up.reshape(-1, 3), masked.reshape(-1)))
+        assert_within(e_up.reshape(-1, 3), masked.reshape(-1))
 
 
 def _full_size_case(torch, oracle, name, scale, samples_low, samples_hi, tile=16):
@@ -110,11 +126,11 @@ def _full_size_case(torch, oracle, name, scale, samples_low, samples_hi, tile=16
     ref = _oracle_nodes(oracle, proj, order, cfg, xs, ys)
     err, masked = best_variant_error(low[ys, xs], ref)
     report(f"e2e_{name}_lowres_sampled", summarize(err, masked, ref["out"]))
-    assert_within(err, masked, max_masked_frac=5e-3)
+    assert_within(err, masked, max_masked_frac=1e-2)
     print(f"e2e {name}: oracle upscaled samples", flush=True)
     e_up, amb = _check_upscaled_samples(oracle, proj, order, cfg, (w, h), (W, H), up, samples_hi, 8)
     report(f"e2e_{name}_x{scale}_upscaled_sampled", summarize(e_up, amb))
-    assert_within(e_up, amb, max_masked_frac=2e-2)
+    assert_within(e_up, amb, max_masked_frac=1e-2)
     return rd, cam, cfg, low, up
 
 
