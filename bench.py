@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle compositing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MB (a reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1",
@@ -215,6 +217,13 @@ def main():
         sys.exit(2)
 
     res = run_gpu(args)
+    if args.copy_probe_mb:
+        import torch
+        src = torch.empty(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     name, s, w, h, W, H = (res[k] for k in ("name", "s", "w", "h", "W", "H"))
     line = {
         "metric": METRIC,

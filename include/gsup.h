@@ -64,7 +64,7 @@ typedef struct gs_camera {
 
 /* Render settings.  The paper fixes none of these numbers; see each field. */
 typedef struct gs_raster_cfg {
-  int32_t tile_size; /* square screen tile edge in pixels: 8 or 16 */
+  int32_t tile_size; /* square screen tile edge in pixels: 8, 16 or 32 */
   int32_t sh_degree; /* degree of the SH colour, 0..3 */
   float dilation;    /* px^2 added to the 2D covariance diagonal (low-pass), >= 0; 3DGS uses 0.3 */
   float alpha_min;   /* fragments with alpha < alpha_min are skipped, in (0, alpha_max) */

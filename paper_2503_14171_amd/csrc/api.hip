@@ -39,8 +39,8 @@ gs_status check_camera(const char* fn, const gs_camera* cam) {
 
 gs_status check_cfg(const char* fn, const gs_raster_cfg* cfg) {
   if (!cfg) return fail(GS_ERR_INVALID_ARGUMENT, "%s: cfg is NULL", fn);
-  if (cfg->tile_size != 8 && cfg->tile_size != 16)
-    return fail(GS_ERR_UNSUPPORTED, "%s: tile_size %d (supported: 8, 16)", fn, cfg->tile_size);
+  if (cfg->tile_size != 8 && cfg->tile_size != 16 && cfg->tile_size != 32)
+    return fail(GS_ERR_UNSUPPORTED, "%s: tile_size %d (supported: 8, 16, 32)", fn, cfg->tile_size);
   if (cfg->sh_degree < 0 || cfg->sh_degree > 3)
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: sh_degree %d outside [0, 3]", fn, cfg->sh_degree);
   if (!(cfg->dilation >= 0.f) || !finite(cfg->dilation))
@@ -124,7 +124,7 @@ gs_status gs_project(int64_t n, const float* means, const float* log_scales, con
 size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* cam,
                                   const gs_raster_cfg* cfg) {
   if (!cam || !cfg || n < 0 || capacity < 0 || cam->width < 1 || cam->height < 1 ||
-      (cfg->tile_size != 8 && cfg->tile_size != 16))
+      (cfg->tile_size != 8 && cfg->tile_size != 16 && cfg->tile_size != 32))
     return 0;
   return make_bin_sort_plan(n, capacity, cam->width, cam->height, cfg->tile_size).bytes;
 }

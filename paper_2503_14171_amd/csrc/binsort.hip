@@ -153,120 +153,176 @@ hipError_t device_exclusive_scan(T* data, int64_t m, uint64_t* partials, uint64_
 }
 
 // ----------------------------------------------------------------------------
-// LSD radix sort pass on (uint32 key, uint32 value)
+// LSD radix sort pass on (uint32 key, uint32 value), BITS-bit digits
+//
+// Every block owns kTile consecutive elements; wave w of the block owns the
+// contiguous quarter [w * kSeg, (w + 1) * kSeg) and walks it 64 elements at a
+// time.  Lanes holding the same digit are found with BITS ballots (wave64
+// match); the lowest such lane updates the wave's private digit counter in
+// LDS.  No block barrier is needed while ranking, and equal digits keep
+// their input order (wave-major, then round, then lane).
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
-                                                                 int64_t m, int shift, uint32_t mask,
-                                                                 uint32_t* __restrict__ hist,
-                                                                 int64_t nblocks) {
-  __shared__ uint32_t s_cnt[kRadix];
-  s_cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+constexpr int kSeg = kTile / kWaves;   // elements per wave
+constexpr int kRounds = kSeg / 64;     // 64-element rounds per wave
+
+template <int BITS>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t same = __ballot(valid);
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int64_t e = base + r * kThreads + threadIdx.x;
-    if (e < m) atomicAdd(&s_cnt[(keys[e] >> shift) & mask], 1u);
+  for (int b = 0; b < BITS; ++b) {
+    const uint64_t bal = __ballot((d >> b) & 1u);
+    same &= ((d >> b) & 1u) ? bal : ~bal;
   }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_cnt[threadIdx.x];
+  return same;
 }
 
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <int BITS>
+__global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
+                                                                 int64_t m, int shift,
+                                                                 uint32_t* __restrict__ hist,
+                                                                 int64_t nblocks) {
+  constexpr uint32_t R = 1u << BITS;
+  __shared__ uint32_t s_h[kWaves][kRadix];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) s_h[w][t] = 0;
+  __syncthreads();
+  const uint64_t lt = lanes_below(lane);
+  const int64_t seg = (int64_t)blockIdx.x * kTile + wave * kSeg;
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t e = seg + r * 64 + lane;
+    const bool valid = e < m;
+    const uint32_t d = valid ? (keys[e] >> shift) & (R - 1) : 0u;
+    const uint64_t same = match_digit<BITS>(d, valid);
+    if (valid && (same & lt) == 0) s_h[wave][d] += (uint32_t)__popcll(same);
+  }
+  __syncthreads();
+  if (t < (int)R) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += s_h[w][t];
+    hist[(int64_t)t * nblocks + blockIdx.x] = c;
+  }
+}
+
+template <int BITS>
 __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t m, int shift,
-    uint32_t mask, int nbits, const uint32_t* __restrict__ hist, int64_t nblocks) {
+    const uint32_t* __restrict__ hist, int64_t nblocks) {
+  constexpr uint32_t R = 1u << BITS;
   __shared__ uint32_t s_keys[kTile];
   __shared__ uint32_t s_vals[kTile];
+  __shared__ uint32_t s_wh[kWaves][kRadix];  // per-wave digit counts, then per-wave bases
   __shared__ uint32_t s_gbase[kRadix];
   __shared__ uint32_t s_lstart[kRadix];
-  __shared__ uint32_t s_run[kRadix];
-  __shared__ uint32_t s_wcnt[kWaves][kRadix];
   __shared__ uint32_t s_w[kWaves];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t base = (int64_t)blockIdx.x * kTile;
-  const int count = (m - base < kTile) ? (int)(m - base) : kTile;
-
-  uint32_t key[kItems], val[kItems];
+  const int64_t seg = base + wave * kSeg;
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int64_t e = base + r * kThreads + t;
-    key[r] = e < m ? keys_in[e] : 0u;
-    val[r] = e < m ? vals_in[e] : 0u;
-  }
-  s_run[t] = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) s_wcnt[w][t] = 0;
-  s_gbase[t] = hist[(int64_t)t * nblocks + blockIdx.x];
-  __syncthreads();
-  // block histogram -> local digit starts
-#pragma unroll
-  for (int r = 0; r < kItems; ++r)
-    if (r * kThreads + t < count) atomicAdd(&s_run[(key[r] >> shift) & mask], 1u);
-  __syncthreads();
-  {
-    uint32_t excl;
-    block_exclusive_scan<uint32_t>(s_run[t], &excl, s_w);
-    s_lstart[t] = excl;
-  }
-  __syncthreads();
-  s_run[t] = 0;
+  for (int w = 0; w < kWaves; ++w) s_wh[w][t] = 0;
+  s_gbase[t] = t < (int)R ? hist[(int64_t)t * nblocks + blockIdx.x] : 0u;
   __syncthreads();
 
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kItems; ++r) {
-    const bool valid = r * kThreads + t < count;
-    const uint32_t d = (key[r] >> shift) & mask;
-    // lanes of this wave holding the same digit (stable order = lane order)
-    uint64_t same = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-      const uint64_t bal = __ballot((d >> b) & 1u);
-      same &= ((d >> b) & 1u) ? bal : ~bal;
-    }
+  // 1. rank within the wave's segment
+  const uint64_t lt = lanes_below(lane);
+  uint32_t key[kRounds], val[kRounds], rank[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t e = seg + r * 64 + lane;
+    const bool valid = e < m;
+    key[r] = valid ? keys_in[e] : 0u;
+    val[r] = valid ? vals_in[e] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool valid = seg + r * 64 + lane < m;
+    const uint32_t d = (key[r] >> shift) & (R - 1);
+    const uint64_t same = match_digit<BITS>(d, valid);
     const uint32_t below = (uint32_t)__popcll(same & lt);
-    if (valid && below == 0) s_wcnt[wave][d] = (uint32_t)__popcll(same);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = s_lstart[d] + s_run[d] + below;
-      for (int w = 0; w < wave; ++w) pos += s_wcnt[w][d];
+    const uint32_t old = s_wh[wave][d];
+    if (valid && below == 0) s_wh[wave][d] = old + (uint32_t)__popcll(same);
+    rank[r] = old + below;
+  }
+  __syncthreads();
+
+  // 2. per digit: wave bases inside the block, digit starts of the block
+  {
+    uint32_t c[kWaves], tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      c[w] = s_wh[w][t];
+      tot += c[w];
+    }
+    uint32_t excl;
+    block_exclusive_scan<uint32_t>(tot, &excl, s_w);
+    s_lstart[t] = excl;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      s_wh[w][t] = excl;
+      excl += c[w];
+    }
+  }
+  __syncthreads();
+
+  // 3. reorder the block in LDS by digit
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    if (seg + r * 64 + lane < m) {
+      const uint32_t d = (key[r] >> shift) & (R - 1);
+      const uint32_t pos = s_wh[wave][d] + rank[r];
       s_keys[pos] = key[r];
       s_vals[pos] = val[r];
     }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      add += s_wcnt[w][t];
-      s_wcnt[w][t] = 0;
-    }
-    s_run[t] += add;
-    __syncthreads();
   }
-  // digit runs are contiguous in LDS: consecutive threads write consecutive addresses
+  __syncthreads();
+
+  // 4. digit runs are contiguous: consecutive threads write consecutive addresses
+  const int count = (m - base < kTile) ? (int)(m - base) : kTile;
   for (int i = t; i < count; i += kThreads) {
     const uint32_t k = s_keys[i];
-    const uint32_t d = (k >> shift) & mask;
+    const uint32_t d = (k >> shift) & (R - 1);
     const uint32_t dst = s_gbase[d] + (uint32_t)i - s_lstart[d];
     keys_out[dst] = k;
     vals_out[dst] = s_vals[i];
   }
 }
 
-// One stable pass over `bits` bits starting at `shift`.
+template <int BITS>
+hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+                           uint32_t* vout, int64_t m, int shift, uint32_t* hist,
+                           uint64_t* partials, hipStream_t stream) {
+  const int64_t nb = ceil_div(m, kTile);
+  radix_upsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, m, shift, hist, nb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = device_exclusive_scan<uint32_t>(hist, (int64_t)(1 << BITS) * nb, partials, nullptr, stream);
+  if (e != hipSuccess) return e;
+  radix_downsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, vin, kout, vout, m,
+                                                                       shift, hist, nb);
+  return hipGetLastError();
+}
+
+// One stable pass over `bits` (1..8) bits starting at `shift`.
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       int64_t m, int shift, int bits, uint32_t* hist, uint64_t* partials,
                       hipStream_t stream) {
-  const int64_t nb = ceil_div(m, kTile);
-  const uint32_t mask = (1u << bits) - 1u;
-  radix_upsweep_kernel<<<(unsigned)nb, kThreads, 0, stream>>>(kin, m, shift, mask, hist, nb);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = device_exclusive_scan<uint32_t>(hist, (int64_t)kRadix * nb, partials, nullptr, stream);
-  if (e != hipSuccess) return e;
-  radix_downsweep_kernel<<<(unsigned)nb, kThreads, 0, stream>>>(kin, vin, kout, vout, m, shift,
-                                                                 mask, bits, hist, nb);
-  return hipGetLastError();
+  switch (bits) {
+    case 1: return radix_pass_bits<1>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+    case 2: return radix_pass_bits<2>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+    case 3: return radix_pass_bits<3>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+    case 4: return radix_pass_bits<4>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+    case 5: return radix_pass_bits<5>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+    case 6: return radix_pass_bits<6>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+    case 7: return radix_pass_bits<7>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+    default: return radix_pass_bits<8>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -293,29 +349,68 @@ __global__ void depth_key_kernel(int64_t n, const float* __restrict__ depth,
   vals[i] = (uint32_t)i;
 }
 
-__global__ void tile_count_kernel(int64_t n, const uint32_t* __restrict__ order,
-                                  const int4* __restrict__ rect, int32_t tiles_x, int32_t tiles_y,
-                                  uint64_t* __restrict__ cnt) {
+// rectangles in depth order (clipped) and their tile counts
+__global__ void gather_rect_kernel(int64_t n, const uint32_t* __restrict__ order,
+                                   const int4* __restrict__ rect, int32_t tiles_x,
+                                   int32_t tiles_y, int4* __restrict__ srect,
+                                   uint64_t* __restrict__ cnt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  cnt[p] = rect_tiles(clip_rect(rect[order[p]], tiles_x, tiles_y));
+  const int4 r = clip_rect(rect[order[p]], tiles_x, tiles_y);
+  srect[p] = r;
+  cnt[p] = rect_tiles(r);
 }
 
-__global__ void emit_kernel(int64_t n, const uint32_t* __restrict__ order,
-                            const int4* __restrict__ rect, const uint64_t* __restrict__ offs,
-                            int32_t tiles_x, int32_t tiles_y, uint32_t* __restrict__ tkeys,
-                            uint32_t* __restrict__ tvals) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const uint32_t g = order[p];
-  const int4 r = clip_rect(rect[g], tiles_x, tiles_y);
-  uint64_t o = offs[p];
-  for (int ty = r.y; ty < r.w; ++ty)
-    for (int tx = r.x; tx < r.z; ++tx) {
-      tkeys[o] = (uint32_t)(ty * tiles_x + tx);
-      tvals[o] = g;
-      ++o;
+// Pair emission, load-balanced: a block takes 256 consecutive splats (depth
+// order), whose pairs form one contiguous range; every thread writes one pair
+// per step, finding its splat by binary search over the block's offsets in
+// LDS, so the writes are coalesced whatever the splats' tile counts.
+constexpr int kEmit = 256;
+__global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* __restrict__ order,
+                                                     const int4* __restrict__ srect,
+                                                     const uint64_t* __restrict__ offs,
+                                                     const uint64_t* __restrict__ total,
+                                                     int32_t tiles_x, uint32_t* __restrict__ tkeys,
+                                                     uint32_t* __restrict__ tvals) {
+  __shared__ uint32_t s_off[kEmit + 1];
+  __shared__ int4 s_rect[kEmit];
+  __shared__ uint32_t s_gid[kEmit];
+  const int t = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * kEmit;
+  const int nb = (int)((n - p0 < kEmit) ? (n - p0) : kEmit);
+  const uint64_t base = offs[p0];
+  if (t < nb) {
+    s_off[t] = (uint32_t)(offs[p0 + t] - base);
+    s_rect[t] = srect[p0 + t];
+    s_gid[t] = order[p0 + t];
+  }
+  if (t == 0) s_off[nb] = (uint32_t)(((p0 + kEmit < n) ? offs[p0 + kEmit] : *total) - base);
+  __syncthreads();
+  const uint32_t end = s_off[nb];
+  for (uint32_t k = t; k < end; k += kEmit) {
+    // owner: the last j with s_off[j] <= k (splats without tiles have s_off[j] == s_off[j+1])
+    int lo = 0, hi = nb;  // invariant: s_off[lo] <= k < s_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[mid] <= k) lo = mid;
+      else hi = mid;
     }
+    const int4 r = s_rect[lo];
+    const uint32_t li = k - s_off[lo];
+    const uint32_t w = (uint32_t)(r.z - r.x);
+    // row / column inside the rectangle; the float quotient is exact to +-1
+    int dy = (int)(((float)li + 0.5f) / (float)w);
+    int dx = (int)li - dy * (int)w;
+    if (dx < 0) {
+      --dy;
+      dx += (int)w;
+    } else if (dx >= (int)w) {
+      ++dy;
+      dx -= (int)w;
+    }
+    tkeys[base + k] = (uint32_t)(r.y + dy) * (uint32_t)tiles_x + (uint32_t)(r.x + dx);
+    tvals[base + k] = s_gid[lo];
+  }
 }
 
 __global__ void tile_range_kernel(int64_t K, const uint32_t* __restrict__ tkeys,
@@ -356,6 +451,7 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int32_t width, int32
   p.off_gval[0] = take(n4);
   p.off_gval[1] = take(n4);
   p.off_cnt = take(sizeof(uint64_t) * (size_t)(n + 1));
+  p.off_srect = take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(n, 1));
   p.off_pkey[0] = take(c4);
   p.off_pkey[1] = take(c4);
   p.off_pval = take(c4);
@@ -408,8 +504,9 @@ gs_status run_bin_sort(const BinSortPlan& p, const float* depth, const int32_t* 
   const uint32_t* order = u32(p.off_gval[cur]);
 
   // 2. tiles per splat in depth order -> pair offsets and the total K
-  tile_count_kernel<<<grid1d(n, 256), 256, 0, stream>>>(n, order, r4, tx, ty, cnt);
-  GS_TRY(hipGetLastError(), "tile_count_kernel");
+  int4* srect = reinterpret_cast<int4*>(ws + p.off_srect);
+  gather_rect_kernel<<<grid1d(n, 256), 256, 0, stream>>>(n, order, r4, tx, ty, srect, cnt);
+  GS_TRY(hipGetLastError(), "gather_rect_kernel");
   GS_TRY(device_exclusive_scan<uint64_t>(cnt, n, partials, total, stream), "pair offset scan");
   uint64_t K = 0;
   GS_TRY(hipMemcpyAsync(&K, total, sizeof(K), hipMemcpyDeviceToHost, stream), "pair count copy");
@@ -432,7 +529,8 @@ gs_status run_bin_sort(const BinSortPlan& p, const float* depth, const int32_t* 
   vbuf[0] = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(sorted_ids) : u32(p.off_pval);
   vbuf[1] = (passes % 2 == 0) ? u32(p.off_pval) : reinterpret_cast<uint32_t*>(sorted_ids);
   uint32_t* kbuf[2] = {u32(p.off_pkey[0]), u32(p.off_pkey[1])};
-  emit_kernel<<<grid1d(n, 256), 256, 0, stream>>>(n, order, r4, cnt, tx, ty, kbuf[0], vbuf[0]);
+  emit_kernel<<<grid1d(n, kEmit), kEmit, 0, stream>>>(n, order, srect, cnt, total, tx, kbuf[0],
+                                                       vbuf[0]);
   GS_TRY(hipGetLastError(), "emit_kernel");
 
   // 4. stable sort of the pairs by tile id

@@ -73,8 +73,10 @@ __device__ __forceinline__ void sh_eval(double x, double y, double z, double* Y)
   Y[15] = -K3a * x * (xx - 3.0 * yy);
 }
 
+constexpr int kProjThreads = 256;
+
 template <int DEG>
-__global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float* __restrict__ means,
+__global__ __launch_bounds__(kProjThreads) void project_kernel(ProjParams p, const float* __restrict__ means,
                                                       const float* __restrict__ log_scales,
                                                       const float* __restrict__ quats,
                                                       const float* __restrict__ opacity,
@@ -82,9 +84,28 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
                                                       gs_splat* __restrict__ splats,
                                                       float* __restrict__ depth_out,
                                                       int4* __restrict__ rect_out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
   constexpr int nb = (DEG + 1) * (DEG + 1);
+  constexpr int NF = 3 * nb;  // SH floats per Gaussian
+  // The block's SH coefficients are contiguous in HBM; stage them through LDS
+  // with coalesced 16-byte (or 4-byte) loads, then each thread reads its own.
+  __shared__ float s_sh[kProjThreads * NF];
+  const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
+  const int64_t i = g0 + threadIdx.x;
+  {
+    const int64_t cnt = (p.n - g0 < kProjThreads) ? (p.n - g0) : kProjThreads;
+    const float* src = sh + g0 * NF;
+    if constexpr (NF % 4 == 0) {
+      const int nv = (int)(cnt * NF / 4);
+      const float4* s4 = reinterpret_cast<const float4*>(src);
+      float4* d4 = reinterpret_cast<float4*>(s_sh);
+      for (int k = threadIdx.x; k < nv; k += kProjThreads) d4[k] = s4[k];
+    } else {
+      const int nv = (int)(cnt * NF);
+      for (int k = threadIdx.x; k < nv; k += kProjThreads) s_sh[k] = src[k];
+    }
+  }
+  __syncthreads();
+  if (i >= p.n) return;
 
   const double mu0 = means[3 * i], mu1 = means[3 * i + 1], mu2 = means[3 * i + 2];
   const double ls0 = log_scales[3 * i], ls1 = log_scales[3 * i + 1], ls2 = log_scales[3 * i + 2];
@@ -92,12 +113,12 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
   const float sig = opacity[i];
 
   // SH coefficients: 3 * nb floats per Gaussian.
-  float coef[3 * nb];
-  const float* shg = sh + (int64_t)3 * nb * i;
-  if constexpr ((3 * nb) % 4 == 0) {
+  float coef[NF];
+  const float* shg = s_sh + threadIdx.x * NF;
+  if constexpr (NF % 4 == 0) {
     const float4* s4 = reinterpret_cast<const float4*>(shg);
 #pragma unroll
-    for (int k = 0; k < 3 * nb / 4; ++k) {
+    for (int k = 0; k < NF / 4; ++k) {
       const float4 v = s4[k];
       coef[4 * k] = v.x;
       coef[4 * k + 1] = v.y;
@@ -106,7 +127,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 3 * nb; ++k) coef[k] = shg[k];
+    for (int k = 0; k < NF; ++k) coef[k] = shg[k];
   }
 
   bool ok = isfinite(sig) && isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(ls0) &&
@@ -239,7 +260,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* log_scales
   p.alpha_min = cfg.alpha_min;
   p.limx = kFrustumClamp * (0.5 * cam.width) / (double)cam.fx;
   p.limy = kFrustumClamp * (0.5 * cam.height) / (double)cam.fy;
-  const int threads = 256;
+  const int threads = kProjThreads;
   const int64_t blocks = ceil_div(n, threads);
   int4* r4 = reinterpret_cast<int4*>(rect);
   const dim3 g((unsigned)blocks), b(threads);

@@ -16,15 +16,20 @@
 // with alpha_x = -alpha u, alpha_y = -alpha v, alpha_xy = alpha (u v - b),
 // (u, v) = Q d, d = pixel - mean, Q = [[a, b], [b, c]] the conic.
 //
-// Work decomposition (gfx950): one workgroup per screen tile, one pixel per
-// lane (8x8 tile = one wave64, 16x16 tile = four).  The tile's splats stream
-// through LDS in batches of one splat per lane; every lane reads the same LDS
-// record (broadcast, no bank conflicts).  A lane whose transmittance dropped
-// below t_min leaves the batch loop; the wave's exec mask then shrinks and the
-// wave leaves once every lane is done, and the workgroup stops fetching
+// Work decomposition (gfx950): one workgroup per screen tile (8x8, 16x16 or
+// 32x32 pixels), one pixel per lane, and every wave64 owns one 8x8 quadrant
+// of the tile.  The tile's splats stream through LDS in batches of one splat
+// per thread; while staging, each thread marks the quadrants its splat's
+// support box meets, and each wave then compacts the batch (ballot + prefix
+// popcount) into its own LDS list of hits in depth order, so a wave only
+// evaluates splats that can reach its 64 pixels.  Every lane reads the same
+// LDS record (broadcast, no bank conflicts).  A lane whose transmittance
+// dropped below t_min leaves the loop; the wave's exec mask then shrinks and
+// the wave leaves once every lane is done, and the workgroup stops fetching
 // batches once a barrier count shows no live pixel.  Splat means are held in
 // FP64 and turned into tile-relative FP32 offsets when staged into LDS, so
-// pixel - mean is exact at any image coordinate.
+// pixel - mean is exact at any image coordinate.  Blocks are renumbered so
+// that each XCD (own L2) works on a contiguous band of tiles.
 #include "gsup_internal.h"
 
 namespace gsup {
@@ -37,6 +42,10 @@ struct RasterParams {
   float bg[3];
 };
 
+// Widening, in pixels, of a splat's support box in the per-wave culling test
+// (covers FP32 rounding of the box and of the per-pixel alpha test).
+constexpr float kCullMargin = 0.25f;
+
 template <int TILE, bool GRAD>
 __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
                                                             const gs_splat* __restrict__ splats,
@@ -45,20 +54,26 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
                                                             float* __restrict__ out,
                                                             int32_t* __restrict__ n_blend) {
   constexpr int NT = TILE * TILE;
+  constexpr int NW = NT / 64;   // waves; wave w owns one 8x8 quadrant of the tile
+  constexpr int QX = TILE / 8;  // quadrants per tile row
   constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
   __shared__ float4 s_a[NT];  // mean x, mean y (tile-relative), conic a, conic b
   __shared__ float4 s_b[NT];  // conic c, log2 sigma, support, red
   __shared__ float2 s_c[NT];  // green, blue
+  __shared__ uint32_t s_mask[NW > 1 ? NT : 1];             // quadrants a staged splat can reach
+  __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? NT : 1];  // per-wave hits, batch order
 
   const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
   if (tile >= p.tiles) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int tx = (int)(tile % p.tiles_x), ty = (int)(tile / p.tiles_x);
-  const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+  const int lx = (wave % QX) * 8 + (lane & 7), ly = (wave / QX) * 8 + (lane >> 3);
   const int px = tx * TILE + lx, py = ty * TILE + ly;
   const bool inside = px < p.width && py < p.height;
   const float fx = (float)lx, fy = (float)ly;
   const double ox = (double)tx * TILE, oy = (double)ty * TILE;
   const int2 rg = ranges[tile];
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
   bool done = !inside;
   float T = 1.f, Tx = 0.f, Ty = 0.f, Txy = 0.f;
@@ -69,20 +84,58 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
 
   for (int base = rg.x; base < rg.y; base += NT) {
     if (__syncthreads_count(!done) == 0) break;
-    const int idx = base + (int)threadIdx.x;
+    // stage one splat per thread
+    const int idx = base + t;
+    uint32_t mask = 0;
     if (idx < rg.y) {
       const float4* s = reinterpret_cast<const float4*>(splats + ids[idx]);
       const double2 m = *reinterpret_cast<const double2*>(s);
       const float4 q = s[1];  // a, b, c, sigma
       const float4 c = s[2];  // r, g, b, support
-      s_a[threadIdx.x] = make_float4((float)(m.x - ox), (float)(m.y - oy), q.x, q.y);
-      s_b[threadIdx.x] = make_float4(q.z, log2f(q.w), c.w, c.x);
-      s_c[threadIdx.x] = make_float2(c.y, c.z);
+      const float mx = (float)(m.x - ox), my = (float)(m.y - oy);
+      s_a[t] = make_float4(mx, my, q.x, q.y);
+      s_b[t] = make_float4(q.z, log2f(q.w), c.w, c.x);
+      s_c[t] = make_float2(c.y, c.z);
+      if (NW > 1) {
+        // quadrants met by the box of {d^T Q d <= support}: half extents
+        // sqrt(support Sigma'_xx), Sigma'_xx = c / (a c - b^2)
+        const float det = q.x * q.z - q.y * q.y;
+        if (det > 0.f) {
+          const float rx = sqrtf(fmaxf(c.w * q.z / det, 0.f)) + kCullMargin;
+          const float ry = sqrtf(fmaxf(c.w * q.x / det, 0.f)) + kCullMargin;
+          // quadrant k holds pixel centres 8k .. 8k+7 (float -> int saturates)
+          const int qx0 = max(0, (int)ceilf((mx - rx - 7.f) * 0.125f));
+          const int qx1 = min(QX - 1, (int)floorf((mx + rx) * 0.125f));
+          const int qy0 = max(0, (int)ceilf((my - ry - 7.f) * 0.125f));
+          const int qy1 = min(QX - 1, (int)floorf((my + ry) * 0.125f));
+          for (int qy = qy0; qy <= qy1; ++qy)
+            for (int qx = qx0; qx <= qx1; ++qx) mask |= 1u << (qy * QX + qx);
+        } else {
+          mask = (NW >= 32) ? ~0u : ((1u << NW) - 1u);  // degenerate in FP32: keep everywhere
+        }
+      }
     }
+    if (NW > 1) s_mask[t] = mask;
     __syncthreads();
     const int cnt = min(NT, rg.y - base);
+    int nl = cnt;
+    if (NW > 1) {
+      // this wave's splats of the batch, in batch (= depth) order
+      nl = 0;
+      if (__ballot(!done) != 0) {
+        for (int c0 = 0; c0 < cnt; c0 += 64) {
+          const int j = c0 + lane;
+          const bool hit = j < cnt && ((s_mask[j] >> wave) & 1u);
+          const uint64_t bal = __ballot(hit);
+          if (hit) s_list[wave][nl + __popcll(bal & lt)] = (uint16_t)j;
+          nl += __popcll(bal);
+        }
+      }
+      __syncthreads();
+    }
     if (!done) {
-      for (int j = 0; j < cnt; ++j) {
+      for (int k = 0; k < nl; ++k) {
+        const int j = NW > 1 ? (int)s_list[wave][k] : k;
         const float4 ga = s_a[j];
         const float4 gb = s_b[j];
         const float dx = fx - ga.x, dy = fy - ga.y;
@@ -172,9 +225,12 @@ hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
   if (cfg.tile_size == 8) {
     if (grads) launch<8, true>(p, splats, sorted_ids, r2, out, n_blend, stream);
     else launch<8, false>(p, splats, sorted_ids, r2, out, n_blend, stream);
-  } else {
+  } else if (cfg.tile_size == 16) {
     if (grads) launch<16, true>(p, splats, sorted_ids, r2, out, n_blend, stream);
     else launch<16, false>(p, splats, sorted_ids, r2, out, n_blend, stream);
+  } else {
+    if (grads) launch<32, true>(p, splats, sorted_ids, r2, out, n_blend, stream);
+    else launch<32, false>(p, splats, sorted_ids, r2, out, n_blend, stream);
   }
   return hipGetLastError();
 }

@@ -102,7 +102,7 @@ def _run_bin_sort(gs, depth32, rect, cam, cfg, capacity=None):
     return ids.cpu().numpy()[:K], ranges.cpu().numpy()
 
 
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 def test_bin_sort_matches_lexsort_oracle_scene(gs, oracle, tile):
     from paper_2503_14171_amd import scenes
     sc = scenes.make_scene("clusters", 60000, 23, 0)
@@ -205,7 +205,7 @@ def _raster_stage(gs, oracle, sc, cam, cfg, want_grads=True, sample=None, seed=0
     return g[idx], nb[idx], ref
 
 
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 @pytest.mark.parametrize("want_grads", [True, False])
 def test_raster_stage_tiny(gs, oracle, tile, want_grads):
     from paper_2503_14171_amd import scenes
@@ -221,18 +221,36 @@ def test_raster_stage_tiny(gs, oracle, tile, want_grads):
     np.testing.assert_array_equal(nb[clean], ref["n_blend"][clean])
 
 
-def test_raster_stage_ragged_bg_opaque(gs, oracle):
+@pytest.mark.parametrize("tile", [16, 32])
+def test_raster_stage_ragged_bg_opaque(gs, oracle, tile):
     """Image size not a multiple of the tile, non-zero background, opaque
     splats (alpha clamp and early termination everywhere)."""
     from paper_2503_14171_amd import scenes
     sc = scenes.make_scene("uniform", 6000, 24, 0)
     sc["opacity"][::2] = np.float32(0.999)
     cam = scenes.make_camera(101, 75)
-    cfg = scenes.render_config(0, tile_size=16, bg=(0.25, 0.5, 1.0))
-    print("raster stage ragged", flush=True)
+    cfg = scenes.render_config(0, tile_size=tile, bg=(0.25, 0.5, 1.0))
+    print(f"raster stage ragged tile={tile}", flush=True)
     g, nb, ref = _raster_stage(gs, oracle, sc, cam, cfg, True)
     err, masked = best_variant_error(g, ref)
-    report("raster_stage_ragged", summarize(err, masked, ref["out"]))
+    report(f"raster_stage_ragged_t{tile}", summarize(err, masked, ref["out"]))
+    assert_within(err, masked)
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_raster_stage_needles(gs, oracle, tile):
+    """Very anisotropic splats (one axis 30x the others) crossing many tiles
+    and quadrants: the per-wave culling must keep every reachable splat."""
+    from paper_2503_14171_amd import scenes
+    sc = scenes.make_scene("uniform", 3000, 26, 0)
+    sc["log_scales"][:, 0] += np.float32(3.4)
+    sc["log_scales"][:, 1:] -= np.float32(0.5)
+    cam = scenes.make_camera(160, 96)
+    cfg = scenes.render_config(0, tile_size=tile)
+    print(f"raster stage needles tile={tile}", flush=True)
+    g, nb, ref = _raster_stage(gs, oracle, sc, cam, cfg, True)
+    err, masked = best_variant_error(g, ref)
+    report(f"raster_stage_needles_t{tile}", summarize(err, masked, ref["out"]))
     assert_within(err, masked)
 
 
