@@ -100,7 +100,8 @@ int64_t gs_num_tiles(int32_t width, int32_t height, int32_t tile_size);
  *                     (graphics sign convention), d = cfg->sh_degree
  * Outputs (device):
  *   splats [n]        gs_splat records (zeroed when culled)
- *   depth [n]         camera-space z rounded to FP32 (the sort key)
+ *   depth [n]         camera-space z rounded to FP32 (the sort key); +inf when the
+ *                     splat reaches no tile (culled or off-screen)
  *   rect [n,4] int32  tile rectangle [tx0, ty0, tx1, ty1) that holds every pixel
  *                     with alpha >= alpha_min; all zero when culled or off-screen
  * A Gaussian is culled when an input is not finite, its camera z <= near_plane,
@@ -119,7 +120,8 @@ size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* 
 /* gs_bin_sort -- per-tile front-to-back lists (the depth order of
  * Sec. "Differentiable 3D Gaussian Splatting", restricted to each tile).
  *
- * Inputs (device): depth [n] and rect [n,4] from gs_project.
+ * Inputs (device): depth [n] and rect [n,4] from gs_project (depth must be
+ * positive, or +inf, wherever rect is non-empty: its bits are the sort key).
  * Outputs:
  *   sorted_ids [capacity] int32  (device) splat indices; tile t's list is
  *                               sorted_ids[tile_ranges[2t] .. tile_ranges[2t+1]),

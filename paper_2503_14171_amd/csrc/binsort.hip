@@ -4,20 +4,23 @@
 // (Sec. "Differentiable 3D Gaussian Splatting").  A tiled rasterizer needs
 // that order restricted to the splats that can reach each tile.  Instead of
 // sorting one 64-bit (tile, depth) key per pair, this implementation
-//   1. sorts the n splats once by their FP32 depth bits (32-bit LSD radix,
-//      4 passes over n elements, stable, so equal depths keep index order),
-//   2. counts the tiles of every splat in that order and scans the counts,
-//   3. emits (tile, splat) pairs in depth order, and
-//   4. stably sorts the pairs by tile id only (ceil(log2 T) bits, 2-3 passes),
+//   1. sorts the n splats once by their FP32 depth bits (stable LSD radix
+//      sort, so equal depths keep index order),
+//   2. gathers the splats' tile rectangles in that order and sums their tile
+//      counts per block of 256 splats (one small scan gives every block's pair
+//      offset and the total K),
+//   3. emits (tile, splat) pairs in depth order, one thread per pair, and
+//   4. stably sorts the pairs by tile id only (ceil(log2 T) bits),
 // which yields each tile's list in (depth, index) order while moving the
-// large pair array only 2-3 times with 8-byte records.
+// large pair array only once or twice with 8-byte records.
 //
-// The radix sort is a reduce-then-scan LSD sort with 8-bit digits: an
-// upsweep kernel histograms each 4096-element block, a device-wide scan turns
-// the digit-major histogram into per-(digit, block) output bases, and a
-// downsweep kernel ranks each block's elements stably (wave64 ballot match
-// plus per-wave counts in LDS), reorders them in LDS and writes every digit
-// run contiguously.
+// Radix passes use digits of up to GSUP_MAX_DIGIT_BITS bits (default 8; the
+// key bits are split evenly over the fewest passes; on MI355X 11-bit digits
+// measured slower: their LDS footprint allows one block per CU): an upsweep kernel histograms each
+// 4096-element block, one workgroup per digit scans that digit's counts over
+// the blocks, and a downsweep kernel ranks each block's elements stably
+// (wave64 ballot match plus wave-private counters in LDS), reorders them in
+// LDS and writes every digit run contiguously.
 #include <algorithm>
 
 #include "gsup_internal.h"
@@ -28,8 +31,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;  // elements per sort / scan block
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
 constexpr int kWaves = kThreads / 64;
 
 // ----------------------------------------------------------------------------
@@ -41,7 +42,7 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
 }
 
 // ----------------------------------------------------------------------------
-// device-wide exclusive scan (reduce-then-scan), T = uint32_t or uint64_t
+// block-level scans (wave64 shuffles + one LDS slot per wave)
 // ----------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
@@ -54,16 +55,18 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
   return v;
 }
 
-// Exclusive scan of one value per thread over the block; returns the block total.
-template <typename T>
+// Exclusive scan of one value per thread over a block of NT threads; returns
+// the block total.  s_w: NT / 64 slots of LDS.
+template <typename T, int NT = kThreads>
 __device__ __forceinline__ T block_exclusive_scan(T v, T* excl, T* s_w) {
+  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const T inc = wave_inclusive_scan(v);
   if (lane == 63) s_w[wave] = inc;
   __syncthreads();
   T wbase = 0, total = 0;
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
+  for (int w = 0; w < NW; ++w) {
     const T s = s_w[w];
     if (w < wave) wbase += s;
     total += s;
@@ -80,80 +83,43 @@ __device__ __forceinline__ void load_blocked(const T* in, int64_t m, int64_t bas
   for (int k = 0; k < kItems; ++k) v[k] = (s + k < m) ? in[s + k] : T(0);
 }
 
+// Exclusive scan of m elements in one workgroup of 1024 threads (chunks of
+// 16384 with a carry); writes the grand total.  For the short arrays of
+// per-block sums.
+constexpr int kSmallThreads = 1024;
 template <typename T>
-__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const T* __restrict__ in, int64_t m,
-                                                               uint64_t* __restrict__ partials) {
-  __shared__ T s_w[kWaves];
-  T v[kItems];
-  load_blocked(in, m, (int64_t)blockIdx.x * kTile, v);
-  T sum = 0;
+__global__ __launch_bounds__(kSmallThreads) void scan_small_kernel(T* __restrict__ data, int64_t m,
+                                                                   T* __restrict__ total) {
+  __shared__ T s_w[kSmallThreads / 64];
+  T carry = 0;
+  for (int64_t base = 0; base < m; base += (int64_t)kSmallThreads * kItems) {
+    T v[kItems];
+    load_blocked(data, m, base, v);
+    T sum = 0;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) sum += v[k];
-  T excl;
-  const T total = block_exclusive_scan(sum, &excl, s_w);
-  if (threadIdx.x == 0) partials[blockIdx.x] = (uint64_t)total;
-}
-
-// Scans `in` (m elements) into `out` (may alias) adding bases[blockIdx.x];
-// with bases == nullptr the block base is 0.  If total != nullptr the block
-// with the last element writes the grand total there.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void scan_down_kernel(const T* in, T* out, int64_t m,
-                                                             const uint64_t* __restrict__ bases,
-                                                             uint64_t* __restrict__ total) {
-  __shared__ T s_w[kWaves];
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  T v[kItems];
-  load_blocked(in, m, base, v);
-  T sum = 0;
+    for (int k = 0; k < kItems; ++k) sum += v[k];
+    T excl;
+    const T tot = block_exclusive_scan<T, kSmallThreads>(sum, &excl, s_w);
+    T run = carry + excl;
+    const int64_t s0 = base + (int64_t)threadIdx.x * kItems;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) sum += v[k];
-  T excl;
-  const T btotal = block_exclusive_scan(sum, &excl, s_w);
-  const T off = bases ? (T)bases[blockIdx.x] : T(0);
-  T run = off + excl;
-  const int64_t s = base + (int64_t)threadIdx.x * kItems;
-#pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    if (s + k < m) out[s + k] = run;
-    run += v[k];
+    for (int k = 0; k < kItems; ++k) {
+      if (s0 + k < m) data[s0 + k] = run;
+      run += v[k];
+    }
+    carry += tot;
   }
-  if (total && threadIdx.x == 0 && base + kTile >= m) *total = (uint64_t)(off + btotal);
-}
-
-// partial-sum storage needed to scan m elements (all recursion levels)
-size_t scan_partials_elems(int64_t m) {
-  size_t s = 0;
-  while (m > kTile) {
-    m = ceil_div(m, kTile);
-    s += (size_t)m;
-  }
-  return s + 1;
-}
-
-// Exclusive scan of m elements of `data` in place.  partials: uint64 scratch of
-// scan_partials_elems(m) elements.  total (optional): device uint64 grand total.
-template <typename T>
-hipError_t device_exclusive_scan(T* data, int64_t m, uint64_t* partials, uint64_t* total,
-                                 hipStream_t stream) {
-  if (m <= 0) return hipSuccess;
-  const int64_t nb = ceil_div(m, kTile);
-  if (nb == 1) {
-    scan_down_kernel<T><<<1, kThreads, 0, stream>>>(data, data, m, nullptr, total);
-    return hipGetLastError();
-  }
-  scan_reduce_kernel<T><<<(unsigned)nb, kThreads, 0, stream>>>(data, m, partials);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // scan the block partials (uint64) recursively; their total is the grand total
-  e = device_exclusive_scan<uint64_t>(partials, nb, partials + nb, total, stream);
-  if (e != hipSuccess) return e;
-  scan_down_kernel<T><<<(unsigned)nb, kThreads, 0, stream>>>(data, data, m, partials, nullptr);
-  return hipGetLastError();
+  if (threadIdx.x == 0) *total = carry;
 }
 
 // ----------------------------------------------------------------------------
-// LSD radix sort pass on (uint32 key, uint32 value), BITS-bit digits
+// LSD radix sort pass on (uint32 key, uint32 value), BITS-bit digits (1..11)
+//
+// upsweep    per-block digit histogram -> hist[digit][block]
+// hist_scan  one workgroup per digit: exclusive scan of that digit's row over
+//            the blocks, plus the digit's total
+// downsweep  per block: digit starts from the totals, stable local ranks,
+//            reorder in LDS, contiguous writes of every digit run
 //
 // Every block owns kTile consecutive elements; wave w of the block owns the
 // contiguous quarter [w * kSeg, (w + 1) * kSeg) and walks it 64 elements at a
@@ -164,6 +130,11 @@ hipError_t device_exclusive_scan(T* data, int64_t m, uint64_t* partials, uint64_
 // ----------------------------------------------------------------------------
 constexpr int kSeg = kTile / kWaves;   // elements per wave
 constexpr int kRounds = kSeg / 64;     // 64-element rounds per wave
+#ifndef GSUP_MAX_DIGIT_BITS
+#define GSUP_MAX_DIGIT_BITS 8
+#endif
+constexpr int kMaxDigitBits = GSUP_MAX_DIGIT_BITS;
+static_assert(kMaxDigitBits >= 1 && kMaxDigitBits <= 11, "digit width");
 
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -185,61 +156,111 @@ __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t*
                                                                  int64_t m, int shift,
                                                                  uint32_t* __restrict__ hist,
                                                                  int64_t nblocks) {
-  constexpr uint32_t R = 1u << BITS;
-  __shared__ uint32_t s_h[kWaves][kRadix];
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t s_h[kWaves][R];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) s_h[w][t] = 0;
-  __syncthreads();
-  const uint64_t lt = lanes_below(lane);
+  for (int k = t; k < kWaves * R; k += kThreads) (&s_h[0][0])[k] = 0;
   const int64_t seg = (int64_t)blockIdx.x * kTile + wave * kSeg;
+  uint32_t key[kRounds];
+#pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t e = seg + r * 64 + lane;
-    const bool valid = e < m;
-    const uint32_t d = valid ? (keys[e] >> shift) & (R - 1) : 0u;
+    key[r] = e < m ? keys[e] : 0u;
+  }
+  __syncthreads();
+  const uint64_t lt = lanes_below(lane);
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool valid = seg + r * 64 + lane < m;
+    const uint32_t d = (key[r] >> shift) & (R - 1);
     const uint64_t same = match_digit<BITS>(d, valid);
     if (valid && (same & lt) == 0) s_h[wave][d] += (uint32_t)__popcll(same);
   }
   __syncthreads();
-  if (t < (int)R) {
+  for (int d = t; d < R; d += kThreads) {
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) c += s_h[w][t];
-    hist[(int64_t)t * nblocks + blockIdx.x] = c;
+    for (int w = 0; w < kWaves; ++w) c += s_h[w][d];
+    hist[(int64_t)d * nblocks + blockIdx.x] = c;
   }
+}
+
+// Block d scans row d of hist (nblocks entries) in place and writes its total.
+__global__ __launch_bounds__(kThreads) void hist_scan_kernel(uint32_t* __restrict__ hist,
+                                                             int64_t nblocks,
+                                                             uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_w[kWaves];
+  uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nblocks; base += kTile) {
+    uint32_t v[kItems];
+    load_blocked(row, nblocks, base, v);
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) sum += v[k];
+    uint32_t excl;
+    const uint32_t tot = block_exclusive_scan<uint32_t>(sum, &excl, s_w);
+    uint32_t run = carry + excl;
+    const int64_t s0 = base + (int64_t)threadIdx.x * kItems;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (s0 + k < nblocks) row[s0 + k] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 template <int BITS>
 __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in /* null: index */,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t m, int shift,
-    const uint32_t* __restrict__ hist, int64_t nblocks) {
-  constexpr uint32_t R = 1u << BITS;
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int64_t nblocks) {
+  constexpr int R = 1 << BITS;
+  constexpr int DPT = R > kThreads ? R / kThreads : 1;  // digits per thread in the digit phases
   __shared__ uint32_t s_keys[kTile];
   __shared__ uint32_t s_vals[kTile];
-  __shared__ uint32_t s_wh[kWaves][kRadix];  // per-wave digit counts, then per-wave bases
-  __shared__ uint32_t s_gbase[kRadix];
-  __shared__ uint32_t s_lstart[kRadix];
+  __shared__ uint32_t s_wh[kWaves][R];  // per-wave digit counts, then per-wave bases
+  __shared__ uint32_t s_gbase[R];
+  __shared__ uint32_t s_lstart[R];
   __shared__ uint32_t s_w[kWaves];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t base = (int64_t)blockIdx.x * kTile;
   const int64_t seg = base + wave * kSeg;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) s_wh[w][t] = 0;
-  s_gbase[t] = t < (int)R ? hist[(int64_t)t * nblocks + blockIdx.x] : 0u;
-  __syncthreads();
+  for (int k = t; k < kWaves * R; k += kThreads) (&s_wh[0][0])[k] = 0;
 
-  // 1. rank within the wave's segment
-  const uint64_t lt = lanes_below(lane);
   uint32_t key[kRounds], val[kRounds], rank[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t e = seg + r * 64 + lane;
     const bool valid = e < m;
     key[r] = valid ? keys_in[e] : 0u;
-    val[r] = valid ? vals_in[e] : 0u;
+    val[r] = valid ? (vals_in ? vals_in[e] : (uint32_t)e) : 0u;
   }
+  // global digit starts (exclusive scan of the totals) + this block's prefix
+  {
+    uint32_t tv[DPT], sum = 0;
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      const int d = t * DPT + k;
+      tv[k] = d < R ? totals[d] : 0u;
+      sum += tv[k];
+    }
+    uint32_t excl;
+    block_exclusive_scan<uint32_t>(sum, &excl, s_w);
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+      const int d = t * DPT + k;
+      if (d < R) s_gbase[d] = excl + hist[(int64_t)d * nblocks + blockIdx.x];
+      excl += tv[k];
+    }
+  }
+  __syncthreads();
+
+  // 1. rank within the wave's segment
+  const uint64_t lt = lanes_below(lane);
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const bool valid = seg + r * 64 + lane < m;
@@ -254,19 +275,33 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
 
   // 2. per digit: wave bases inside the block, digit starts of the block
   {
-    uint32_t c[kWaves], tot = 0;
+    uint32_t c[DPT][kWaves], tot[DPT], sum = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      c[w] = s_wh[w][t];
-      tot += c[w];
+    for (int k = 0; k < DPT; ++k) {
+      const int d = t * DPT + k;
+      tot[k] = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        c[k][w] = d < R ? s_wh[w][d] : 0u;
+        tot[k] += c[k][w];
+      }
+      sum += tot[k];
     }
     uint32_t excl;
-    block_exclusive_scan<uint32_t>(tot, &excl, s_w);
-    s_lstart[t] = excl;
+    block_exclusive_scan<uint32_t>(sum, &excl, s_w);
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      s_wh[w][t] = excl;
-      excl += c[w];
+    for (int k = 0; k < DPT; ++k) {
+      const int d = t * DPT + k;
+      if (d < R) {
+        s_lstart[d] = excl;
+        uint32_t run = excl;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          s_wh[w][d] = run;
+          run += c[k][w];
+        }
+      }
+      excl += tot[k];
     }
   }
   __syncthreads();
@@ -297,32 +332,53 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
 template <int BITS>
 hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                            uint32_t* vout, int64_t m, int shift, uint32_t* hist,
-                           uint64_t* partials, hipStream_t stream) {
+                           uint32_t* totals, hipStream_t stream) {
   const int64_t nb = ceil_div(m, kTile);
   radix_upsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, m, shift, hist, nb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = device_exclusive_scan<uint32_t>(hist, (int64_t)(1 << BITS) * nb, partials, nullptr, stream);
+  hist_scan_kernel<<<1u << BITS, kThreads, 0, stream>>>(hist, nb, totals);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   radix_downsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, vin, kout, vout, m,
-                                                                       shift, hist, nb);
+                                                                       shift, hist, totals, nb);
   return hipGetLastError();
 }
 
-// One stable pass over `bits` (1..8) bits starting at `shift`.
+// One stable pass over `bits` (1..kMaxDigitBits) bits starting at `shift`.
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                      int64_t m, int shift, int bits, uint32_t* hist, uint64_t* partials,
+                      int64_t m, int shift, int bits, uint32_t* hist, uint32_t* totals,
                       hipStream_t stream) {
   switch (bits) {
-    case 1: return radix_pass_bits<1>(kin, vin, kout, vout, m, shift, hist, partials, stream);
-    case 2: return radix_pass_bits<2>(kin, vin, kout, vout, m, shift, hist, partials, stream);
-    case 3: return radix_pass_bits<3>(kin, vin, kout, vout, m, shift, hist, partials, stream);
-    case 4: return radix_pass_bits<4>(kin, vin, kout, vout, m, shift, hist, partials, stream);
-    case 5: return radix_pass_bits<5>(kin, vin, kout, vout, m, shift, hist, partials, stream);
-    case 6: return radix_pass_bits<6>(kin, vin, kout, vout, m, shift, hist, partials, stream);
-    case 7: return radix_pass_bits<7>(kin, vin, kout, vout, m, shift, hist, partials, stream);
-    default: return radix_pass_bits<8>(kin, vin, kout, vout, m, shift, hist, partials, stream);
+#define GS_RADIX_CASE(B)                                                                  \
+  case B:                                                                                 \
+    if (B <= kMaxDigitBits)                                                               \
+      return radix_pass_bits<(B <= kMaxDigitBits ? B : 1)>(kin, vin, kout, vout, m, shift, \
+                                                           hist, totals, stream);         \
+    break;
+    GS_RADIX_CASE(1)
+    GS_RADIX_CASE(2)
+    GS_RADIX_CASE(3)
+    GS_RADIX_CASE(4)
+    GS_RADIX_CASE(5)
+    GS_RADIX_CASE(6)
+    GS_RADIX_CASE(7)
+    GS_RADIX_CASE(8)
+    GS_RADIX_CASE(9)
+    GS_RADIX_CASE(10)
+    GS_RADIX_CASE(11)
+#undef GS_RADIX_CASE
+    default: break;
   }
+  return hipErrorInvalidValue;
+}
+
+// Splits `bits` key bits into the fewest passes of at most kMaxDigitBits,
+// as evenly as possible; returns the pass count and fills widths[].
+int radix_plan(int bits, int widths[8]) {
+  const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+  for (int k = 0; k < passes; ++k) widths[k] = bits / passes + (k < bits % passes ? 1 : 0);
+  return passes;
 }
 
 // ----------------------------------------------------------------------------
@@ -337,57 +393,61 @@ __device__ __forceinline__ uint32_t rect_tiles(int4 r) {
   return (uint32_t)(max(r.z - r.x, 0) * max(r.w - r.y, 0));
 }
 
-// depth key of splat i: FP32 bits (monotone for depth > 0); splats that reach
-// no tile sort last.
-__global__ void depth_key_kernel(int64_t n, const float* __restrict__ depth,
-                                 const int4* __restrict__ rect, int32_t tiles_x, int32_t tiles_y,
-                                 uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int4 r = clip_rect(rect[i], tiles_x, tiles_y);
-  keys[i] = rect_tiles(r) ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
-  vals[i] = (uint32_t)i;
+constexpr int kEmit = 256;  // splats per gather / emit block
+
+// Rectangles in depth order (clipped) and, per block of kEmit splats, the sum
+// of their tile counts.
+__global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
+                                                            const uint32_t* __restrict__ order,
+                                                            const int4* __restrict__ rect,
+                                                            int32_t tiles_x, int32_t tiles_y,
+                                                            int4* __restrict__ srect,
+                                                            uint64_t* __restrict__ bsum) {
+  __shared__ uint64_t s_w[kEmit / 64];
+  const int64_t p = (int64_t)blockIdx.x * kEmit + threadIdx.x;
+  uint64_t c = 0;
+  if (p < n) {
+    const int4 r = clip_rect(rect[order[p]], tiles_x, tiles_y);
+    srect[p] = r;
+    c = rect_tiles(r);
+  }
+  uint64_t excl;
+  const uint64_t tot = block_exclusive_scan<uint64_t>(c, &excl, s_w);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// rectangles in depth order (clipped) and their tile counts
-__global__ void gather_rect_kernel(int64_t n, const uint32_t* __restrict__ order,
-                                   const int4* __restrict__ rect, int32_t tiles_x,
-                                   int32_t tiles_y, int4* __restrict__ srect,
-                                   uint64_t* __restrict__ cnt) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int4 r = clip_rect(rect[order[p]], tiles_x, tiles_y);
-  srect[p] = r;
-  cnt[p] = rect_tiles(r);
-}
-
-// Pair emission, load-balanced: a block takes 256 consecutive splats (depth
-// order), whose pairs form one contiguous range; every thread writes one pair
-// per step, finding its splat by binary search over the block's offsets in
-// LDS, so the writes are coalesced whatever the splats' tile counts.
-constexpr int kEmit = 256;
+// Pair emission, load-balanced: a block takes kEmit consecutive splats (depth
+// order), whose pairs form one contiguous range starting at boff[block]; the
+// block scans its splats' tile counts in LDS, then every thread writes one
+// pair per step, finding its splat by binary search over those offsets, so
+// the writes are coalesced whatever the splats' tile counts.  Only runs once
+// the total is known to be below 2^31.
 __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* __restrict__ order,
                                                      const int4* __restrict__ srect,
-                                                     const uint64_t* __restrict__ offs,
-                                                     const uint64_t* __restrict__ total,
+                                                     const uint64_t* __restrict__ boff,
                                                      int32_t tiles_x, uint32_t* __restrict__ tkeys,
                                                      uint32_t* __restrict__ tvals) {
   __shared__ uint32_t s_off[kEmit + 1];
   __shared__ int4 s_rect[kEmit];
   __shared__ uint32_t s_gid[kEmit];
+  __shared__ uint32_t s_w[kEmit / 64];
   const int t = threadIdx.x;
   const int64_t p0 = (int64_t)blockIdx.x * kEmit;
   const int nb = (int)((n - p0 < kEmit) ? (n - p0) : kEmit);
-  const uint64_t base = offs[p0];
+  uint32_t c = 0;
   if (t < nb) {
-    s_off[t] = (uint32_t)(offs[p0 + t] - base);
-    s_rect[t] = srect[p0 + t];
+    const int4 r = srect[p0 + t];
+    s_rect[t] = r;
     s_gid[t] = order[p0 + t];
+    c = rect_tiles(r);
   }
-  if (t == 0) s_off[nb] = (uint32_t)(((p0 + kEmit < n) ? offs[p0 + kEmit] : *total) - base);
+  uint32_t excl;
+  const uint32_t tot = block_exclusive_scan<uint32_t>(c, &excl, s_w);
+  s_off[t] = excl;
+  if (t == 0) s_off[nb] = tot;
   __syncthreads();
-  const uint32_t end = s_off[nb];
-  for (uint32_t k = t; k < end; k += kEmit) {
+  const uint64_t base = boff[blockIdx.x];
+  for (uint32_t k = t; k < tot; k += kEmit) {
     // owner: the last j with s_off[j] <= k (splats without tiles have s_off[j] == s_off[j+1])
     int lo = 0, hi = nb;  // invariant: s_off[lo] <= k < s_off[hi]
     while (hi - lo > 1) {
@@ -413,13 +473,25 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
   }
 }
 
-__global__ void tile_range_kernel(int64_t K, const uint32_t* __restrict__ tkeys,
-                                  int32_t* __restrict__ ranges) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= K) return;
-  const uint32_t t = tkeys[p];
-  if (p == 0 || tkeys[p - 1] != t) ranges[2 * (int64_t)t] = (int32_t)p;
-  if (p == K - 1 || tkeys[p + 1] != t) ranges[2 * (int64_t)t + 1] = (int32_t)(p + 1);
+// Tile ranges from the tile-sorted keys: a block stages kTile keys plus one
+// neighbour on each side in LDS and marks where the tile id changes.
+__global__ __launch_bounds__(kThreads) void tile_range_kernel(int64_t K,
+                                                              const uint32_t* __restrict__ tkeys,
+                                                              int32_t* __restrict__ ranges) {
+  __shared__ uint32_t s_k[kTile + 2];
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  for (int i = threadIdx.x; i < kTile + 2; i += kThreads) {
+    const int64_t p = base + i - 1;
+    s_k[i] = (p >= 0 && p < K) ? tkeys[p] : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kTile; i += kThreads) {
+    const int64_t p = base + i;
+    if (p >= K) break;
+    const uint32_t t = s_k[i + 1];
+    if (p == 0 || s_k[i] != t) ranges[2 * (int64_t)t] = (int32_t)p;
+    if (p == K - 1 || s_k[i + 2] != t) ranges[2 * (int64_t)t + 1] = (int32_t)(p + 1);
+  }
 }
 
 inline unsigned grid1d(int64_t n, int threads) { return (unsigned)ceil_div(n, threads); }
@@ -444,23 +516,22 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int32_t width, int32
     off = align_up(off + bytes, A);
     return o;
   };
-  const size_t n4 = sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1);
+  const int64_t n1 = std::max<int64_t>(n, 1);
+  const size_t n4 = sizeof(uint32_t) * (size_t)n1;
   const size_t c4 = sizeof(uint32_t) * (size_t)std::max<int64_t>(capacity, 1);
   p.off_gkey[0] = take(n4);
   p.off_gkey[1] = take(n4);
   p.off_gval[0] = take(n4);
   p.off_gval[1] = take(n4);
-  p.off_cnt = take(sizeof(uint64_t) * (size_t)(n + 1));
-  p.off_srect = take(sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(n, 1));
+  p.off_bsum = take(sizeof(uint64_t) * (size_t)ceil_div(n1, kEmit));
+  p.off_srect = take(sizeof(int32_t) * 4 * (size_t)n1);
   p.off_pkey[0] = take(c4);
   p.off_pkey[1] = take(c4);
   p.off_pval = take(c4);
-  const int64_t max_blocks = std::max<int64_t>(ceil_div(std::max<int64_t>(n, 1), kTile),
+  const int64_t max_blocks = std::max<int64_t>(ceil_div(n1, kTile),
                                                ceil_div(std::max<int64_t>(capacity, 1), kTile));
-  const int64_t hist_elems = (int64_t)kRadix * max_blocks;
-  p.off_hist = take(sizeof(uint32_t) * (size_t)hist_elems);
-  const size_t part = std::max(scan_partials_elems(hist_elems), scan_partials_elems(n + 1));
-  p.off_scan = take(sizeof(uint64_t) * part);
+  p.off_hist = take(sizeof(uint32_t) * (size_t)((int64_t(1) << kMaxDigitBits) * max_blocks));
+  p.off_totals = take(sizeof(uint32_t) * (size_t)(1 << kMaxDigitBits));
   p.off_total = take(sizeof(uint64_t));
   p.bytes = off;
   return p;
@@ -471,9 +542,9 @@ gs_status run_bin_sort(const BinSortPlan& p, const float* depth, const int32_t* 
                        void* workspace, hipStream_t stream) {
   char* ws = static_cast<char*>(workspace);
   auto u32 = [&](size_t o) { return reinterpret_cast<uint32_t*>(ws + o); };
-  uint64_t* cnt = reinterpret_cast<uint64_t*>(ws + p.off_cnt);
+  uint64_t* bsum = reinterpret_cast<uint64_t*>(ws + p.off_bsum);
   uint32_t* hist = u32(p.off_hist);
-  uint64_t* partials = reinterpret_cast<uint64_t*>(ws + p.off_scan);
+  uint32_t* totals = u32(p.off_totals);
   uint64_t* total = reinterpret_cast<uint64_t*>(ws + p.off_total);
   const int4* r4 = reinterpret_cast<const int4*>(rect);
   const int64_t n = p.n;
@@ -489,25 +560,31 @@ gs_status run_bin_sort(const BinSortPlan& p, const float* depth, const int32_t* 
     fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
     return check_hip(hipGetLastError(), "fill_i32_kernel");
   }
-  // 1. depth order of all splats (4 stable 8-bit passes over the FP32 bits)
+  // 1. depth order of all splats: stable LSD radix sort of the FP32 depth bits
+  //    (positive floats order like their bits; +inf marks splats without
+  //    tiles); the first pass reads the depths in place and numbers them
   const int32_t tx = (int32_t)p.tiles_x, ty = (int32_t)p.tiles_y;
-  depth_key_kernel<<<grid1d(n, 256), 256, 0, stream>>>(n, depth, r4, tx, ty, u32(p.off_gkey[0]),
-                                                        u32(p.off_gval[0]));
-  GS_TRY(hipGetLastError(), "depth_key_kernel");
-  int cur = 0;
-  for (int shift = 0; shift < 32; shift += kRadixBits) {
-    GS_TRY(radix_pass(u32(p.off_gkey[cur]), u32(p.off_gval[cur]), u32(p.off_gkey[cur ^ 1]),
-                      u32(p.off_gval[cur ^ 1]), n, shift, kRadixBits, hist, partials, stream),
+  int widths[8];
+  int passes = radix_plan(32, widths);
+  int cur = 0, shift = 0;
+  for (int k = 0; k < passes; ++k) {
+    const uint32_t* kin = k == 0 ? reinterpret_cast<const uint32_t*>(depth) : u32(p.off_gkey[cur]);
+    const uint32_t* vin = k == 0 ? nullptr : u32(p.off_gval[cur]);
+    GS_TRY(radix_pass(kin, vin, u32(p.off_gkey[cur ^ 1]), u32(p.off_gval[cur ^ 1]), n, shift,
+                      widths[k], hist, totals, stream),
            "depth radix pass");
+    shift += widths[k];
     cur ^= 1;
   }
   const uint32_t* order = u32(p.off_gval[cur]);
 
-  // 2. tiles per splat in depth order -> pair offsets and the total K
+  // 2. rectangles in depth order, pair offsets per block of splats, total K
   int4* srect = reinterpret_cast<int4*>(ws + p.off_srect);
-  gather_rect_kernel<<<grid1d(n, 256), 256, 0, stream>>>(n, order, r4, tx, ty, srect, cnt);
+  const int64_t nbe = ceil_div(n, kEmit);
+  gather_rect_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, r4, tx, ty, srect, bsum);
   GS_TRY(hipGetLastError(), "gather_rect_kernel");
-  GS_TRY(device_exclusive_scan<uint64_t>(cnt, n, partials, total, stream), "pair offset scan");
+  scan_small_kernel<uint64_t><<<1, kSmallThreads, 0, stream>>>(bsum, nbe, total);
+  GS_TRY(hipGetLastError(), "pair offset scan");
   uint64_t K = 0;
   GS_TRY(hipMemcpyAsync(&K, total, sizeof(K), hipMemcpyDeviceToHost, stream), "pair count copy");
   GS_TRY(hipStreamSynchronize(stream), "pair count sync");
@@ -523,28 +600,27 @@ gs_status run_bin_sort(const BinSortPlan& p, const float* depth, const int32_t* 
   fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
   GS_TRY(hipGetLastError(), "fill_i32_kernel");
   if (K == 0) return GS_OK;
-  const int passes = (p.tile_bits + kRadixBits - 1) / kRadixBits;
+  passes = radix_plan(p.tile_bits, widths);
   // values end in sorted_ids after `passes` ping-pong steps
   uint32_t* vbuf[2];
   vbuf[0] = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(sorted_ids) : u32(p.off_pval);
   vbuf[1] = (passes % 2 == 0) ? u32(p.off_pval) : reinterpret_cast<uint32_t*>(sorted_ids);
   uint32_t* kbuf[2] = {u32(p.off_pkey[0]), u32(p.off_pkey[1])};
-  emit_kernel<<<grid1d(n, kEmit), kEmit, 0, stream>>>(n, order, srect, cnt, total, tx, kbuf[0],
-                                                       vbuf[0]);
+  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, srect, bsum, tx, kbuf[0], vbuf[0]);
   GS_TRY(hipGetLastError(), "emit_kernel");
 
   // 4. stable sort of the pairs by tile id
   cur = 0;
+  shift = 0;
   for (int k = 0; k < passes; ++k) {
-    const int shift = k * kRadixBits;
-    const int bits = std::min(kRadixBits, p.tile_bits - shift);
-    GS_TRY(radix_pass(kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], (int64_t)K, shift, bits,
-                      hist, partials, stream),
+    GS_TRY(radix_pass(kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], (int64_t)K, shift,
+                      widths[k], hist, totals, stream),
            "tile radix pass");
+    shift += widths[k];
     cur ^= 1;
   }
-  tile_range_kernel<<<grid1d((int64_t)K, 256), 256, 0, stream>>>((int64_t)K, kbuf[cur],
-                                                                  tile_ranges);
+  tile_range_kernel<<<(unsigned)ceil_div((int64_t)K, kTile), kThreads, 0, stream>>>(
+      (int64_t)K, kbuf[cur], tile_ranges);
   GS_TRY(hipGetLastError(), "tile_range_kernel");
 #undef GS_TRY
   return GS_OK;

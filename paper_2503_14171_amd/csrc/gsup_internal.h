@@ -44,12 +44,12 @@ struct BinSortPlan {
   int tile_bits = 0;      // bits of the tile id key
   // workspace layout (byte offsets)
   size_t off_gkey[2], off_gval[2];  // depth keys / splat ids, ping-pong [n]
-  size_t off_cnt;                   // per sorted splat tile count -> offsets [n + 1]
+  size_t off_bsum;                  // tile-count sums per block of splats -> pair offsets
   size_t off_srect;                 // clipped tile rectangles in depth order [n]
   size_t off_pkey[2];               // pair tile keys, ping-pong [capacity]
   size_t off_pval;                  // pair ids, second buffer [capacity]
-  size_t off_hist;                  // radix digit counts [256 * max blocks]
-  size_t off_scan;                  // scan partial sums
+  size_t off_hist;                  // radix digit counts [2^11 * max blocks]
+  size_t off_totals;                // per-digit totals [2^11]
   size_t off_total;                 // 1 x uint64 pair total
   size_t bytes = 0;
 };

@@ -8,10 +8,11 @@
 //
 // One thread per Gaussian.  The geometry is evaluated in FP64: MI355X runs
 // FP64 vector FMAs at the FP32 rate and the kernel is bound by HBM traffic
-// (236 B/Gaussian at SH degree 3), so the extra precision is free; it keeps
-// the FP32-stored conic and the FP64-stored mean accurate to the last bit,
-// which the derivative buffers need (their sensitivity to the mean grows as
-// 1/sigma_px^3).
+// (236 B/Gaussian at SH degree 3), so the extra precision costs little; it
+// keeps the FP32-stored conic and the FP64-stored mean accurate to the last
+// bit, which the derivative buffers need (their sensitivity to the mean grows
+// as 1/sigma_px^3).  The SH colour, which does not depend on the pixel, is
+// summed in FP32.
 #include <cmath>
 
 #include "gsup_internal.h"
@@ -46,37 +47,35 @@ struct ProjParams {
 // K3b = sqrt(105/pi)/2, K3c = sqrt(21/(2 pi))/4, K3d = sqrt(7/pi)/4,
 // K3e = sqrt(105/pi)/4.
 template <int DEG>
-__device__ __forceinline__ void sh_eval(double x, double y, double z, double* Y) {
-  const double K0 = 0.28209479177387814, K1 = 0.4886025119029199;
-  const double K2a = 1.0925484305920792, K2b = 0.31539156525252005, K2c = 0.5462742152960396;
-  const double K3a = 0.5900435899266435, K3b = 2.890611442640554, K3c = 0.4570457994644658,
-               K3d = 0.3731763325901154, K3e = 1.445305721320277;
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
+  const float K0 = 0.28209479177387814f, K1 = 0.4886025119029199f;
+  const float K2a = 1.0925484305920792f, K2b = 0.31539156525252005f, K2c = 0.5462742152960396f;
+  const float K3a = 0.5900435899266435f, K3b = 2.890611442640554f, K3c = 0.4570457994644658f,
+              K3d = 0.3731763325901154f, K3e = 1.445305721320277f;
   Y[0] = K0;
   if (DEG < 1) return;
   Y[1] = -K1 * y;
   Y[2] = K1 * z;
   Y[3] = -K1 * x;
   if (DEG < 2) return;
-  const double xx = x * x, yy = y * y, zz = z * z;
+  const float xx = x * x, yy = y * y, zz = z * z;
   Y[4] = K2a * x * y;
   Y[5] = -K2a * y * z;
-  Y[6] = K2b * (2.0 * zz - xx - yy);
+  Y[6] = K2b * (2.f * zz - xx - yy);
   Y[7] = -K2a * x * z;
   Y[8] = K2c * (xx - yy);
   if (DEG < 3) return;
-  Y[9] = -K3a * y * (3.0 * xx - yy);
+  Y[9] = -K3a * y * (3.f * xx - yy);
   Y[10] = K3b * x * y * z;
-  Y[11] = -K3c * y * (4.0 * zz - xx - yy);
-  Y[12] = K3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-  Y[13] = -K3c * x * (4.0 * zz - xx - yy);
+  Y[11] = -K3c * y * (4.f * zz - xx - yy);
+  Y[12] = K3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+  Y[13] = -K3c * x * (4.f * zz - xx - yy);
   Y[14] = K3e * z * (xx - yy);
-  Y[15] = -K3a * x * (xx - 3.0 * yy);
+  Y[15] = -K3a * x * (xx - 3.f * yy);
 }
 
-constexpr int kProjThreads = 256;
-
 template <int DEG>
-__global__ __launch_bounds__(kProjThreads) void project_kernel(ProjParams p, const float* __restrict__ means,
+__global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float* __restrict__ means,
                                                       const float* __restrict__ log_scales,
                                                       const float* __restrict__ quats,
                                                       const float* __restrict__ opacity,
@@ -84,28 +83,9 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(ProjParams p, con
                                                       gs_splat* __restrict__ splats,
                                                       float* __restrict__ depth_out,
                                                       int4* __restrict__ rect_out) {
-  constexpr int nb = (DEG + 1) * (DEG + 1);
-  constexpr int NF = 3 * nb;  // SH floats per Gaussian
-  // The block's SH coefficients are contiguous in HBM; stage them through LDS
-  // with coalesced 16-byte (or 4-byte) loads, then each thread reads its own.
-  __shared__ float s_sh[kProjThreads * NF];
-  const int64_t g0 = (int64_t)blockIdx.x * kProjThreads;
-  const int64_t i = g0 + threadIdx.x;
-  {
-    const int64_t cnt = (p.n - g0 < kProjThreads) ? (p.n - g0) : kProjThreads;
-    const float* src = sh + g0 * NF;
-    if constexpr (NF % 4 == 0) {
-      const int nv = (int)(cnt * NF / 4);
-      const float4* s4 = reinterpret_cast<const float4*>(src);
-      float4* d4 = reinterpret_cast<float4*>(s_sh);
-      for (int k = threadIdx.x; k < nv; k += kProjThreads) d4[k] = s4[k];
-    } else {
-      const int nv = (int)(cnt * NF);
-      for (int k = threadIdx.x; k < nv; k += kProjThreads) s_sh[k] = src[k];
-    }
-  }
-  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
+  constexpr int nb = (DEG + 1) * (DEG + 1);
 
   const double mu0 = means[3 * i], mu1 = means[3 * i + 1], mu2 = means[3 * i + 2];
   const double ls0 = log_scales[3 * i], ls1 = log_scales[3 * i + 1], ls2 = log_scales[3 * i + 2];
@@ -113,12 +93,12 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(ProjParams p, con
   const float sig = opacity[i];
 
   // SH coefficients: 3 * nb floats per Gaussian.
-  float coef[NF];
-  const float* shg = s_sh + threadIdx.x * NF;
-  if constexpr (NF % 4 == 0) {
+  float coef[3 * nb];
+  const float* shg = sh + (int64_t)3 * nb * i;
+  if constexpr ((3 * nb) % 4 == 0) {
     const float4* s4 = reinterpret_cast<const float4*>(shg);
 #pragma unroll
-    for (int k = 0; k < NF / 4; ++k) {
+    for (int k = 0; k < 3 * nb / 4; ++k) {
       const float4 v = s4[k];
       coef[4 * k] = v.x;
       coef[4 * k + 1] = v.y;
@@ -127,7 +107,7 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(ProjParams p, con
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < NF; ++k) coef[k] = shg[k];
+    for (int k = 0; k < 3 * nb; ++k) coef[k] = shg[k];
   }
 
   bool ok = isfinite(sig) && isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(ls0) &&
@@ -212,20 +192,20 @@ __global__ __launch_bounds__(kProjThreads) void project_kernel(ProjParams p, con
         dy = 0.0;
         dz = 1.0;
       }
-      double Y[nb];
-      sh_eval<DEG>(dx, dy, dz, Y);
-      double col[3] = {0.5, 0.5, 0.5};
+      float Y[nb];
+      sh_eval<DEG>((float)dx, (float)dy, (float)dz, Y);
+      float col[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int k = 0; k < nb; ++k) {
-        col[0] += Y[k] * (double)coef[3 * k];
-        col[1] += Y[k] * (double)coef[3 * k + 1];
-        col[2] += Y[k] * (double)coef[3 * k + 2];
+        col[0] = fmaf(Y[k], coef[3 * k], col[0]);
+        col[1] = fmaf(Y[k], coef[3 * k + 1], col[1]);
+        col[2] = fmaf(Y[k], coef[3 * k + 2], col[2]);
       }
       m2 = make_double2(mx, my);
       w0 = make_float4((float)(syy * id), (float)(-sxy * id), (float)(sxx * id), sig);
-      w1 = make_float4((float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0),
-                       (float)fmax(col[2], 0.0), (float)(2.0 * L));
-      dep = (float)t2;
+      w1 = make_float4(fmaxf(col[0] + 0.5f, 0.f), fmaxf(col[1] + 0.5f, 0.f),
+                       fmaxf(col[2] + 0.5f, 0.f), (float)(2.0 * L));
+      dep = (rect.z > rect.x) ? (float)t2 : INFINITY;
     }
   }
   double2* sp = reinterpret_cast<double2*>(splats + i);
@@ -260,7 +240,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* log_scales
   p.alpha_min = cfg.alpha_min;
   p.limx = kFrustumClamp * (0.5 * cam.width) / (double)cam.fx;
   p.limy = kFrustumClamp * (0.5 * cam.height) / (double)cam.fy;
-  const int threads = kProjThreads;
+  const int threads = 256;
   const int64_t blocks = ceil_div(n, threads);
   int4* r4 = reinterpret_cast<int4*>(rect);
   const dim3 g((unsigned)blocks), b(threads);

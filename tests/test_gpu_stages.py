@@ -75,7 +75,7 @@ def test_project_matches_oracle(gs, oracle, case):
         np.testing.assert_allclose(mean[live], pr["mean2d"][live], rtol=0, atol=1e-9)
         np.testing.assert_allclose(s[live, 4:7], pr["conic"][live], rtol=2e-7, atol=1e-12)
         np.testing.assert_array_equal(s[live, 7], sc["opacity"][live])
-        np.testing.assert_allclose(s[live, 8:11], pr["rgb"][live], rtol=0, atol=2e-7)
+        np.testing.assert_allclose(s[live, 8:11], pr["rgb"][live], rtol=0, atol=1e-6)
         amin = float(np.float32(cfg["alpha_min"]))
         np.testing.assert_allclose(s[live, 11], 2 * np.log(pr["opacity"][live] / amin), rtol=2e-7)
         # culled Gaussians: no tiles, zeroed record, infinite depth
