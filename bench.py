@@ -38,6 +38,23 @@ FLOP_PER_BLEND = {True: 64, False: 25}
 # Bytes the upscaler must move: 48 per low-res pixel read, 12 per output pixel written
 UPSCALE_BYTES_LO, UPSCALE_BYTES_HI = 48, 12
 
+PROFILES = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of `kernel` from the committed counter profile,
+    or None when the kernel's source has changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(PROFILES))[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["sha256"]:
+        return None
+    return int(1024 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]))
+
+
 WORKLOADS = {
     "scene_x4": ("scene", 4), "scene_x3": ("scene", 3), "scene_x2": ("scene", 2),
     "clusters_x2": ("clusters", 2), "tiny_x2": ("tiny", 2),
@@ -245,12 +262,13 @@ def main():
         "roofline": {"kernel": "gs_raster_grad", "bound": "alu",
                      "achieved": round(res["achieved_tflops"], 3), "peak": FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(res["achieved_tflops"] / FP32_VALU_TFLOPS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic("gs_raster_grad") if (args.workload, args.tile) == ("scene_x4", 16) else None,
                      "units": f"{res['frags']} blended fragments x {FLOP_PER_BLEND[True]} FLOP"},
         "upscaler_roofline": {"kernel": "gs_upscale_hermite", "bound": "hbm",
                               "achieved": round(res["up_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(res["up_gbs"] / HBM_PEAK_GBS, 4),
-                              "bytes": res["up_bytes"], "traffic": None},
+                              "bytes": res["up_bytes"],
+                              "traffic": measured_traffic("gs_upscale_hermite") if args.workload == "scene_x4" else None},
         "stages_ms": {k: round(v, 4) for k, v in res["stages_ms"].items()},
         "direct": {"value": round(res["direct"]["value"], 2), "unit": "Mpix/s",
                    "ms_per_frame": round(res["direct"]["ms_per_frame"], 4),

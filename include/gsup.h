@@ -99,13 +99,14 @@ int64_t gs_num_tiles(int32_t width, int32_t height, int32_t tile_size);
  *   sh [n,(d+1)^2,3]  SH coefficients, real orthonormal basis ordered l^2+l+m
  *                     (graphics sign convention), d = cfg->sh_degree
  * Outputs (device):
- *   splats [n]        gs_splat records (zeroed when culled)
+ *   splats [n]        gs_splat records (zeroed for splats that reach no tile)
  *   depth [n]         camera-space z rounded to FP32 (the sort key); +inf when the
  *                     splat reaches no tile (culled or off-screen)
  *   rect [n,4] int32  tile rectangle [tx0, ty0, tx1, ty1) that holds every pixel
  *                     with alpha >= alpha_min; all zero when culled or off-screen
  * A Gaussian is culled when an input is not finite, its camera z <= near_plane,
- * its 2D covariance is not positive definite, or sigma < alpha_min.
+ * its 2D covariance is not positive definite, or sigma < alpha_min.  The SH
+ * coefficients of a Gaussian are read only when its rectangle is not empty.
  * The Jacobian J is evaluated with the mean's direction clamped to 1.3x the
  * half field of view.  n == 0 is a no-op. */
 gs_status gs_project(int64_t n, const float* means, const float* log_scales, const float* quats,

@@ -36,7 +36,7 @@ struct ProjParams {
   double cam[3];
   double near_plane;
   double dilation;
-  double alpha_min;
+  double alpha_min, log_alpha_min;
   double limx, limy;
 };
 
@@ -92,29 +92,9 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
   const float4 q4 = reinterpret_cast<const float4*>(quats)[i];
   const float sig = opacity[i];
 
-  // SH coefficients: 3 * nb floats per Gaussian.
-  float coef[3 * nb];
-  const float* shg = sh + (int64_t)3 * nb * i;
-  if constexpr ((3 * nb) % 4 == 0) {
-    const float4* s4 = reinterpret_cast<const float4*>(shg);
-#pragma unroll
-    for (int k = 0; k < 3 * nb / 4; ++k) {
-      const float4 v = s4[k];
-      coef[4 * k] = v.x;
-      coef[4 * k + 1] = v.y;
-      coef[4 * k + 2] = v.z;
-      coef[4 * k + 3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 3 * nb; ++k) coef[k] = shg[k];
-  }
-
   bool ok = isfinite(sig) && isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(ls0) &&
             isfinite(ls1) && isfinite(ls2) && isfinite(q4.x) && isfinite(q4.y) &&
             isfinite(q4.z) && isfinite(q4.w);
-#pragma unroll
-  for (int k = 0; k < 3 * nb; ++k) ok = ok && isfinite(coef[k]);
 
   const double* V = p.V;
   // camera-space position, summed left to right (products of FP32 values are
@@ -140,11 +120,11 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
                       {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
     const double s2[3] = {exp(2.0 * ls0), exp(2.0 * ls1), exp(2.0 * ls2)};
     // M = J W (2x3); Sigma' = M R S^2 R^T M^T = (M R) S^2 (M R)^T
-    const double tz = t2;
-    const double ux = fmin(p.limx, fmax(-p.limx, t0 / tz)) * tz;
-    const double uy = fmin(p.limy, fmax(-p.limy, t1 / tz)) * tz;
-    const double j00 = p.fx / tz, j02 = -p.fx * ux / (tz * tz);
-    const double j11 = p.fy / tz, j12 = -p.fy * uy / (tz * tz);
+    const double tz = t2, itz = 1.0 / t2;
+    const double ux = fmin(p.limx, fmax(-p.limx, t0 * itz)) * tz;
+    const double uy = fmin(p.limy, fmax(-p.limy, t1 * itz)) * tz;
+    const double j00 = p.fx * itz, j02 = -p.fx * ux * itz * itz;
+    const double j11 = p.fy * itz, j12 = -p.fy * uy * itz * itz;
     double M[2][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -165,10 +145,9 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
     }
     const double det = sxx * syy - sxy * sxy;
     if (det > 0.0) {
-      const double id = 1.0 / det;
-      const double mx = p.fx * t0 / tz + p.cx;
-      const double my = p.fy * t1 / tz + p.cy;
-      const double L = log((double)sig / p.alpha_min);
+      const double mx = p.fx * t0 * itz + p.cx;
+      const double my = p.fy * t1 * itz + p.cy;
+      const double L = log((double)sig) - p.log_alpha_min;
       const double rx = sqrt(2.0 * L * sxx), ry = sqrt(2.0 * L * syy);
       double x0 = ceil(mx - rx - kRectMargin), x1 = floor(mx + rx + kRectMargin);
       double y0 = ceil(my - ry - kRectMargin), y1 = floor(my + ry + kRectMargin);
@@ -177,35 +156,60 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
       x1 = fmin(x1, (double)(p.width - 1));
       y1 = fmin(y1, (double)(p.height - 1));
       if (x0 <= x1 && y0 <= y1) {
-        rect = make_int4((int)x0 / p.tile, (int)y0 / p.tile, (int)x1 / p.tile + 1,
-                         (int)y1 / p.tile + 1);
-      }
-      // view-dependent colour
-      double dx = mu0 - p.cam[0], dy = mu1 - p.cam[1], dz = mu2 - p.cam[2];
-      const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-      if (dn > 0.0) {
-        dx /= dn;
-        dy /= dn;
-        dz /= dn;
-      } else {
-        dx = 0.0;
-        dy = 0.0;
-        dz = 1.0;
-      }
-      float Y[nb];
-      sh_eval<DEG>((float)dx, (float)dy, (float)dz, Y);
-      float col[3] = {0.f, 0.f, 0.f};
+        // On screen: only now read the SH coefficients (3 nb floats), so the
+        // splats that reach no tile cost no colour traffic.
+        float coef[3 * nb];
+        const float* shg = sh + (int64_t)3 * nb * i;
+        if constexpr ((3 * nb) % 4 == 0) {
+          const float4* s4 = reinterpret_cast<const float4*>(shg);
 #pragma unroll
-      for (int k = 0; k < nb; ++k) {
-        col[0] = fmaf(Y[k], coef[3 * k], col[0]);
-        col[1] = fmaf(Y[k], coef[3 * k + 1], col[1]);
-        col[2] = fmaf(Y[k], coef[3 * k + 2], col[2]);
+          for (int k = 0; k < 3 * nb / 4; ++k) {
+            const float4 v = s4[k];
+            coef[4 * k] = v.x;
+            coef[4 * k + 1] = v.y;
+            coef[4 * k + 2] = v.z;
+            coef[4 * k + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 3 * nb; ++k) coef[k] = shg[k];
+        }
+        bool fin = true;
+#pragma unroll
+        for (int k = 0; k < 3 * nb; ++k) fin = fin && isfinite(coef[k]);
+        if (fin) {
+          // view-dependent colour
+          double dx = mu0 - p.cam[0], dy = mu1 - p.cam[1], dz = mu2 - p.cam[2];
+          const double dn2 = dx * dx + dy * dy + dz * dz;
+          if (dn2 > 0.0) {
+            const double idn = 1.0 / sqrt(dn2);
+            dx *= idn;
+            dy *= idn;
+            dz *= idn;
+          } else {
+            dx = 0.0;
+            dy = 0.0;
+            dz = 1.0;
+          }
+          float Y[nb];
+          sh_eval<DEG>((float)dx, (float)dy, (float)dz, Y);
+          float col[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+          for (int k = 0; k < nb; ++k) {
+            col[0] = fmaf(Y[k], coef[3 * k], col[0]);
+            col[1] = fmaf(Y[k], coef[3 * k + 1], col[1]);
+            col[2] = fmaf(Y[k], coef[3 * k + 2], col[2]);
+          }
+          const double id = 1.0 / det;
+          rect = make_int4((int)x0 / p.tile, (int)y0 / p.tile, (int)x1 / p.tile + 1,
+                           (int)y1 / p.tile + 1);
+          m2 = make_double2(mx, my);
+          w0 = make_float4((float)(syy * id), (float)(-sxy * id), (float)(sxx * id), sig);
+          w1 = make_float4(fmaxf(col[0] + 0.5f, 0.f), fmaxf(col[1] + 0.5f, 0.f),
+                           fmaxf(col[2] + 0.5f, 0.f), (float)(2.0 * L));
+          dep = (float)t2;
+        }
       }
-      m2 = make_double2(mx, my);
-      w0 = make_float4((float)(syy * id), (float)(-sxy * id), (float)(sxx * id), sig);
-      w1 = make_float4(fmaxf(col[0] + 0.5f, 0.f), fmaxf(col[1] + 0.5f, 0.f),
-                       fmaxf(col[2] + 0.5f, 0.f), (float)(2.0 * L));
-      dep = (rect.z > rect.x) ? (float)t2 : INFINITY;
     }
   }
   double2* sp = reinterpret_cast<double2*>(splats + i);
@@ -238,6 +242,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* log_scales
   p.near_plane = cam.near_plane;
   p.dilation = cfg.dilation;
   p.alpha_min = cfg.alpha_min;
+  p.log_alpha_min = log((double)cfg.alpha_min);
   p.limx = kFrustumClamp * (0.5 * cam.width) / (double)cam.fx;
   p.limy = kFrustumClamp * (0.5 * cam.height) / (double)cam.fy;
   const int threads = 256;

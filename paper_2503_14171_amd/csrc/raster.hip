@@ -135,48 +135,50 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
     }
     if (!done) {
       for (int k = 0; k < nl; ++k) {
-        const int j = NW > 1 ? (int)s_list[wave][k] : k;
-        const float4 ga = s_a[j];
-        const float4 gb = s_b[j];
-        const float dx = fx - ga.x, dy = fy - ga.y;
-        const float u = fmaf(ga.z, dx, ga.w * dy);  // (Q d)_x
-        const float v = fmaf(ga.w, dx, gb.x * dy);  // (Q d)_y
-        const float q = fmaf(dx, u, dy * v);        // d^T Q d
-        if (q > gb.z) continue;                     // alpha < alpha_min
-        const float2 gc = s_c[j];
-        float alpha = exp2f(fmaf(q, -kHalfLog2e, gb.y));
-        const bool clamp = alpha > p.alpha_max;
-        alpha = clamp ? p.alpha_max : alpha;
-        const float w = T * alpha;
-        if (GRAD) {
-          const float ax = clamp ? 0.f : -alpha * u;
-          const float ay = clamp ? 0.f : -alpha * v;
-          const float axy = clamp ? 0.f : alpha * fmaf(u, v, -ga.w);
-          const float kx = fmaf(T, ax, Tx * alpha);
-          const float ky = fmaf(T, ay, Ty * alpha);
-          const float kxy = fmaf(T, axy, fmaf(Tx, ay, fmaf(Ty, ax, Txy * alpha)));
-          Bx0 = fmaf(gb.w, kx, Bx0);
-          Bx1 = fmaf(gc.x, kx, Bx1);
-          Bx2 = fmaf(gc.y, kx, Bx2);
-          By0 = fmaf(gb.w, ky, By0);
-          By1 = fmaf(gc.x, ky, By1);
-          By2 = fmaf(gc.y, ky, By2);
-          Bxy0 = fmaf(gb.w, kxy, Bxy0);
-          Bxy1 = fmaf(gc.x, kxy, Bxy1);
-          Bxy2 = fmaf(gc.y, kxy, Bxy2);
-          Tx -= kx;
-          Ty -= ky;
-          Txy -= kxy;
+        if (!done) {
+          const int j = NW > 1 ? (int)s_list[wave][k] : k;
+          const float4 ga = s_a[j];
+          const float4 gb = s_b[j];
+          const float dx = fx - ga.x, dy = fy - ga.y;
+          const float u = fmaf(ga.z, dx, ga.w * dy);  // (Q d)_x
+          const float v = fmaf(ga.w, dx, gb.x * dy);  // (Q d)_y
+          const float q = fmaf(dx, u, dy * v);        // d^T Q d
+          if (q <= gb.z) {                            // alpha >= alpha_min
+            const float2 gc = s_c[j];
+            // the exponent is >= log2(alpha_min) > -126: no denormal handling needed
+            float alpha = __builtin_amdgcn_exp2f(fmaf(q, -kHalfLog2e, gb.y));
+            const bool clamp = alpha > p.alpha_max;
+            alpha = clamp ? p.alpha_max : alpha;
+            const float w = T * alpha;
+            if (GRAD) {
+              const float ax = clamp ? 0.f : -alpha * u;
+              const float ay = clamp ? 0.f : -alpha * v;
+              const float axy = clamp ? 0.f : alpha * fmaf(u, v, -ga.w);
+              const float kx = fmaf(T, ax, Tx * alpha);
+              const float ky = fmaf(T, ay, Ty * alpha);
+              const float kxy = fmaf(T, axy, fmaf(Tx, ay, fmaf(Ty, ax, Txy * alpha)));
+              Bx0 = fmaf(gb.w, kx, Bx0);
+              Bx1 = fmaf(gc.x, kx, Bx1);
+              Bx2 = fmaf(gc.y, kx, Bx2);
+              By0 = fmaf(gb.w, ky, By0);
+              By1 = fmaf(gc.x, ky, By1);
+              By2 = fmaf(gc.y, ky, By2);
+              Bxy0 = fmaf(gb.w, kxy, Bxy0);
+              Bxy1 = fmaf(gc.x, kxy, Bxy1);
+              Bxy2 = fmaf(gc.y, kxy, Bxy2);
+              Tx -= kx;
+              Ty -= ky;
+              Txy -= kxy;
+            }
+            B0 = fmaf(gb.w, w, B0);
+            B1 = fmaf(gc.x, w, B1);
+            B2 = fmaf(gc.y, w, B2);
+            T -= w;
+            ++nb;
+            done = T < p.t_min;
+          }
         }
-        B0 = fmaf(gb.w, w, B0);
-        B1 = fmaf(gc.x, w, B1);
-        B2 = fmaf(gc.y, w, B2);
-        T -= w;
-        ++nb;
-        if (T < p.t_min) {
-          done = true;
-          break;
-        }
+        if (__ballot(!done) == 0) break;  // every pixel of the wave is done
       }
     }
   }
