@@ -55,10 +55,17 @@ def measured_traffic(kernel: str):
     return int(1024 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]))
 
 
-WORKLOADS = {
-    "scene_x4": ("scene", 4), "scene_x3": ("scene", 3), "scene_x2": ("scene", 2),
-    "clusters_x2": ("clusters", 2), "tiny_x2": ("tiny", 2),
+WORKLOADS = {  # (scene, x factor, y factor); fractional and per-axis factors use the same mapping
+    "scene_x4": ("scene", 4, 4), "scene_x3": ("scene", 3, 3), "scene_x2": ("scene", 2, 2),
+    "scene_x2.5": ("scene", 2.5, 2.5), "scene_x1.5": ("scene", 1.5, 1.5),
+    "scene_x4_x3": ("scene", 4, 3),
+    "clusters_x2": ("clusters", 2, 2), "tiny_x2": ("tiny", 2, 2),
 }
+
+
+def _psnr(a, b):
+    mse = ((a - b) ** 2).mean().item()
+    return 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
 
 
 def _events(torch, n):
@@ -71,12 +78,13 @@ def run_gpu(args):
     from paper_2503_14171_amd import scenes
     from paper_2503_14171_amd.render import Renderer
 
-    name, s = WORKLOADS[args.workload]
+    name, sx, sy = WORKLOADS[args.workload]
     sc = scenes.workload_scene(name)
     cam = scenes.workload_camera(name)
     cfg = scenes.render_config(sc["sh_degree"], tile_size=args.tile)
     w, h = cam["width"], cam["height"]
-    W, H = w * s, h * s
+    W, H = round(w * sx), round(h * sy)
+    s = sx if sx == sy else [sx, sy]
     cam_hi = scenes.scale_camera(cam, W, H)
     torch.cuda.set_device(0)
     rd = Renderer(sc)
@@ -119,38 +127,79 @@ def run_gpu(args):
     stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])
     st_ms = stage.mean(0)
 
-    # direct full-resolution render (plain compositing) on the same GPU
+    # direct full-resolution render (plain compositing) on the same GPU, with
+    # the frame's own tile size and with the other tile sizes; the best one
+    # is the baseline the speed-up is quoted against
     direct_out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
 
-    def direct_step(ev=None):
-        if ev:
-            ev[0].record()
-        b = rd.project(cam_hi, cfg)
-        if ev:
-            ev[1].record()
-        rd.bin_sort(cam_hi, cfg, b)
-        if ev:
-            ev[2].record()
-        rd.raster(cam_hi, cfg, False, direct_out, b=b)
-        if ev:
-            ev[3].record()
+    def time_direct(tile):
+        cfg_d = dict(cfg, tile_size=tile)
 
-    for _ in range(max(1, args.warmup)):
-        direct_step()
+        def direct_step(ev=None):
+            if ev:
+                ev[0].record()
+            b = rd.project(cam_hi, cfg_d)
+            if ev:
+                ev[1].record()
+            rd.bin_sort(cam_hi, cfg_d, b)
+            if ev:
+                ev[2].record()
+            rd.raster(cam_hi, cfg_d, False, direct_out, b=b)
+            if ev:
+                ev[3].record()
+
+        for _ in range(max(1, args.warmup)):
+            direct_step()
+        torch.cuda.synchronize()
+        devs = [_events(torch, 4) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            direct_step(devs[k])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in devs]).mean(0)
+        rd._bufs.pop((W, H, tile), None)  # free this tile size's buffers
+        return ms, st
+
+    direct_all = {}
+    for tile in sorted({args.tile, 16, 32}):
+        direct_all[tile] = time_direct(tile)
+    best_tile = min(direct_all, key=lambda t: direct_all[t][0])
+    ms_direct, dstage = direct_all[args.tile]
     torch.cuda.synchronize()
-    devs = [_events(torch, 4) for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        direct_step(devs[k])
-    torch.cuda.synchronize()
-    ms_direct = 1e3 * (time.perf_counter() - t0) / args.steps
-    dstage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in devs]).mean(0)
+    rd.render(cam_hi, cfg, False, direct_out)  # the reference image for PSNR
 
     # quality of the upscaled frame against the direct render
     up = ups[(args.warmup + args.steps - 1) % nsets].clamp(0, 1)
     ref = direct_out.clamp(0, 1)
-    mse = torch.mean((up - ref) ** 2).item()
-    psnr = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+    psnr = _psnr(up, ref)
+
+    # comparators on the same low-res colour: classical bicubic (finite-
+    # difference slopes through the same Hermite kernel = Catmull-Rom) and
+    # torch's bicubic (Keys a = -3/4); quality only, plus the slope kernel's time
+    from paper_2503_14171_amd import _lib
+    lo_last = lows[(args.warmup + args.steps - 1) % nsets]
+    rgb_lo = lo_last[..., :3].contiguous()
+    fd_in = torch.empty((h, w, 12), dtype=torch.float32, device="cuda")
+    fd_up = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    fev = _events(torch, 3)
+    _lib.gs_fd_slopes(rgb_lo, fd_in)
+    fev[0].record()
+    for _ in range(10):
+        _lib.gs_fd_slopes(rgb_lo, fd_in)
+    fev[1].record()
+    for _ in range(10):
+        rd.upscale(fd_in, W, H, fd_up)
+    fev[2].record()
+    torch.cuda.synchronize()
+    psnr_fd = _psnr(fd_up.clamp(0, 1), ref)
+    tb = torch.nn.functional.interpolate(rgb_lo.permute(2, 0, 1)[None], size=(H, W), mode="bicubic",
+                                         align_corners=False)[0].permute(1, 2, 0)
+    psnr_torch = _psnr(tb.clamp(0, 1), ref)
+    del tb, fd_up
+    comparators = dict(psnr_fd_bicubic=psnr_fd, psnr_torch_bicubic=psnr_torch,
+                       fd_slopes_ms=fev[0].elapsed_time(fev[1]) / 10,
+                       fd_upscale_ms=fev[1].elapsed_time(fev[2]) / 10)
 
     # algorithmic work of the raster launch: blended fragments (one extra,
     # untimed launch with the per-pixel counter)
@@ -158,7 +207,8 @@ def run_gpu(args):
     rd.render(cam, cfg, True, lows[0], nbl)
     frags = int(nbl.sum().item())
     nbl_hi = torch.empty((H, W), dtype=torch.int32, device="cuda")
-    rd.render(cam_hi, cfg, False, direct_out, nbl_hi)
+    direct_ref = torch.empty_like(direct_out)
+    rd.render(cam_hi, cfg, False, direct_ref, nbl_hi)
     frags_hi = int(nbl_hi.sum().item())
     pairs = rd._bufs[(w, h, cfg["tile_size"])]["n_pairs"]
     pairs_hi = rd._bufs[(W, H, cfg["tile_size"])]["n_pairs"]
@@ -169,7 +219,10 @@ def run_gpu(args):
     up_gbs = up_bytes / (st_ms[3] * 1e-3) / 1e9
     value = W * H / (ms_step * 1e-3) / 1e6
     direct_value = W * H / (ms_direct * 1e-3) / 1e6
-    return dict(
+    best = dict(tile=best_tile, ms_per_frame=direct_all[best_tile][0],
+                value=W * H / (direct_all[best_tile][0] * 1e-3) / 1e6,
+                by_tile={t: round(v[0], 4) for t, v in direct_all.items()})
+    return dict(best_direct=best, comparators=comparators,
         name=name, s=s, w=w, h=h, W=W, H=H, n=rd.n, cfg=cfg, value=value, ms_step=ms_step,
         stages_ms=dict(project=st_ms[0], bin_sort=st_ms[1], raster_grad=st_ms[2], upscale=st_ms[3]),
         direct=dict(value=direct_value, ms_per_frame=ms_direct,
@@ -274,7 +327,15 @@ def main():
                    "ms_per_frame": round(res["direct"]["ms_per_frame"], 4),
                    "stages_ms": {k: round(v, 4) for k, v in res["direct"]["stages_ms"].items()}},
         "speedup_vs_direct": round(res["value"] / res["direct"]["value"], 3),
+        "direct_best": {"tile": res["best_direct"]["tile"], "value": round(res["best_direct"]["value"], 2),
+                        "ms_per_frame": round(res["best_direct"]["ms_per_frame"], 4),
+                        "ms_by_tile": res["best_direct"]["by_tile"]},
+        "speedup_vs_best_direct": round(res["value"] / res["best_direct"]["value"], 3),
         "psnr_vs_direct_db": round(res["psnr"], 2),
+        "comparators": {"psnr_fd_bicubic_db": round(res["comparators"]["psnr_fd_bicubic"], 2),
+                        "psnr_torch_bicubic_db": round(res["comparators"]["psnr_torch_bicubic"], 2),
+                        "fd_slopes_ms": round(res["comparators"]["fd_slopes_ms"], 4),
+                        "fd_upscale_ms": round(res["comparators"]["fd_upscale_ms"], 4)},
         "pairs": {"lowres": res["pairs"], "direct": res["direct"]["pairs"]},
     }
     if not args.no_cpu_baseline:

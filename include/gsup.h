@@ -176,6 +176,17 @@ gs_status gs_raster_grad(const gs_splat* splats, const int32_t* sorted_ids,
 gs_status gs_upscale_hermite(const float* in, int32_t w, int32_t h, float* out, int32_t W,
                              int32_t H, void* stream);
 
+/* gs_fd_slopes -- the classical bicubic comparator: derivative buffers of a
+ * plain image estimated by finite differences (Sec. "Image Gradient Based
+ * Upscaling", Spline Interpolation: classical bicubic interpolation estimates
+ * the gradients with finite differences of neighbouring pixels; Sec.
+ * "Motivational Example").  Feeding the result to gs_upscale_hermite gives
+ * Catmull-Rom (Keys a = -1/2) bicubic upscaling on interior cells.
+ * img [h, w, 3] (device) -> out [h, w, 12] (device, 16-byte aligned, no
+ * overlap): values, f_x = (f[x+1] - f[x-1]) / 2, f_y likewise, f_xy = the
+ * y-difference of f_x; one-sided differences on the border rows/columns. */
+gs_status gs_fd_slopes(const float* img, int32_t w, int32_t h, float* out, void* stream);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char* gs_last_error_message(void);
 

@@ -302,3 +302,23 @@ def tile_lists(depth32: np.ndarray, rect: np.ndarray, tiles_x: int, tiles_y: int
     ranges = np.stack([starts, starts + counts], 1)
     ranges[counts == 0] = 0  # an empty tile's range is [0, 0)
     return gid[o].astype(np.int32), ranges.astype(np.int32)
+
+
+def fd_slopes(img: np.ndarray) -> np.ndarray:
+    """Classical bicubic input: [h, w, 3] -> [h, w, 12] with central-difference
+    slopes (one-sided on the border), f_xy the y-difference of f_x (Sec. "Image
+    Gradient Based Upscaling": classical bicubic estimates gradients with
+    finite differences)."""
+    f = np.asarray(img, np.float64)
+
+    def d(a, axis):
+        n = a.shape[axis]
+        idx = np.arange(n)
+        lo, hi = np.maximum(idx - 1, 0), np.minimum(idx + 1, n - 1)
+        sc = np.where(hi - lo == 2, 0.5, 1.0)
+        shape = [1] * a.ndim
+        shape[axis] = n
+        return (np.take(a, hi, axis) - np.take(a, lo, axis)) * sc.reshape(shape)
+
+    fx = d(f, 1)
+    return np.concatenate([f, fx, d(f, 0), d(fx, 0)], axis=2)

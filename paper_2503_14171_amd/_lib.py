@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
         L.gs_raster_grad.restype = ctypes.c_int
         L.gs_upscale_hermite.argtypes = [P, i32, i32, P, i32, i32, P]
         L.gs_upscale_hermite.restype = ctypes.c_int
+        L.gs_fd_slopes.argtypes = [P, i32, i32, P, P]
+        L.gs_fd_slopes.restype = ctypes.c_int
         L.gs_last_error_message.restype = ctypes.c_char_p
         L.gs_version.restype = ctypes.c_char_p
         _lib = L
@@ -172,3 +174,11 @@ def gs_upscale_hermite(inp, out, stream=None) -> None:
         raise ValueError("inp must be [h, w, 12] and out [H, W, 3]")
     _check(lib().gs_upscale_hermite(_ptr(inp, torch.float32), w, h, _ptr(out, torch.float32), W, H,
                                     _stream(stream)))
+
+
+def gs_fd_slopes(img, out, stream=None) -> None:
+    """img [h, w, 3] -> out [h, w, 12] with finite-difference slopes."""
+    h, w = img.shape[0], img.shape[1]
+    if img.shape[2] != 3 or tuple(out.shape) != (h, w, 12):
+        raise ValueError("img must be [h, w, 3] and out [h, w, 12]")
+    _check(lib().gs_fd_slopes(_ptr(img, torch.float32), w, h, _ptr(out, torch.float32), _stream(stream)))

@@ -197,4 +197,21 @@ gs_status gs_upscale_hermite(const float* in, int32_t w, int32_t h, float* out, 
                    "gs_upscale_hermite launch");
 }
 
+gs_status gs_fd_slopes(const float* img, int32_t w, int32_t h, float* out, void* stream) {
+  g_msg[0] = 0;
+  const char* fn = "gs_fd_slopes";
+  if (!img || !out) return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
+  if (w < 2 || h < 2 || w > kMaxSide || h > kMaxSide)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: image %d x %d outside [2, %d]", fn, w, h, kMaxSide);
+  if (!aligned(img, 4) || !aligned(out, 16))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: out must be 16-byte aligned", fn);
+  const char* ib = reinterpret_cast<const char*>(img);
+  const char* ie = ib + (size_t)w * h * 3 * sizeof(float);
+  const char* ob = reinterpret_cast<const char*>(out);
+  const char* oe = ob + (size_t)w * h * 12 * sizeof(float);
+  if (ib < oe && ob < ie) return fail(GS_ERR_INVALID_ARGUMENT, "%s: img and out overlap", fn);
+  return check_hip(launch_fd_slopes(img, w, h, out, static_cast<hipStream_t>(stream)),
+                   "gs_fd_slopes launch");
+}
+
 }  // extern "C"

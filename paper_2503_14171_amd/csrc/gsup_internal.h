@@ -68,5 +68,7 @@ hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
 // ---- upscaling (upscale.hip) ---------------------------------------------------
 hipError_t launch_upscale(const float* in, int32_t w, int32_t h, float* out, int32_t W,
                           int32_t H, hipStream_t stream);
+hipError_t launch_fd_slopes(const float* img, int32_t w, int32_t h, float* out,
+                            hipStream_t stream);
 
 }  // namespace gsup

@@ -71,10 +71,14 @@ __device__ __forceinline__ void row_terms(const float* __restrict__ in, int w, i
 template <int ROWS>
 __global__ __launch_bounds__(kThreads) void upscale_kernel(const float* __restrict__ in, int w,
                                                            int h, float* __restrict__ out, int W,
-                                                           int H) {
-  const int X = blockIdx.x * kThreads + threadIdx.x;
-  if (X >= W) return;
-  const int Y0 = blockIdx.y * ROWS;
+                                                           int H, int strips) {
+  // bands of one XCD are contiguous, so the low-res row two bands share is
+  // fetched into one L2
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int bx = (int)(blk % strips), by = (int)(blk / strips);
+  const int X = bx * kThreads + threadIdx.x;
+  const int Y0 = by * ROWS;
+  if (X >= W || Y0 >= H) return;
   const int Y1 = min(Y0 + ROWS, H);
   int i;
   float tx;
@@ -117,8 +121,53 @@ __global__ __launch_bounds__(kThreads) void upscale_kernel(const float* __restri
 hipError_t launch_upscale(const float* in, int32_t w, int32_t h, float* out, int32_t W, int32_t H,
                           hipStream_t stream) {
   constexpr int kRows = 16;
-  const dim3 grid((unsigned)ceil_div(W, kThreads), (unsigned)ceil_div(H, kRows));
-  upscale_kernel<kRows><<<grid, kThreads, 0, stream>>>(in, w, h, out, W, H);
+  const int strips = (int)ceil_div(W, kThreads);
+  const int64_t blocks = xcd_grid((int64_t)strips * ceil_div(H, kRows));
+  upscale_kernel<kRows><<<(unsigned)blocks, kThreads, 0, stream>>>(in, w, h, out, W, H, strips);
+  return hipGetLastError();
+}
+
+}  // namespace gsup
+
+namespace gsup {
+namespace {
+
+// Classical bicubic comparator: central-difference slopes of a plain image.
+// f_x = (f[i+1] - f[i-1]) / 2 inside, one-sided differences on the border
+// columns; f_y likewise on rows; f_xy = the y-difference of f_x.
+__device__ __forceinline__ float diff(const float* __restrict__ img, int64_t stride_px, int i, int n,
+                                      int64_t base, int c) {
+  const int lo = i > 0 ? i - 1 : 0, hi = i < n - 1 ? i + 1 : n - 1;
+  const float sc = (hi - lo == 2) ? 0.5f : 1.f;
+  return sc * (img[(base + (int64_t)hi * stride_px) * 3 + c] - img[(base + (int64_t)lo * stride_px) * 3 + c]);
+}
+
+__global__ __launch_bounds__(kThreads) void fd_slopes_kernel(const float* __restrict__ img, int w,
+                                                             int h, float* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= (int64_t)w * h) return;
+  const int x = (int)(p % w), y = (int)(p / w);
+  const int y0 = y > 0 ? y - 1 : 0, y1 = y < h - 1 ? y + 1 : h - 1;
+  const float sy = (y1 - y0 == 2) ? 0.5f : 1.f;
+  float o[12];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    o[c] = img[p * 3 + c];
+    o[3 + c] = diff(img, 1, x, w, (int64_t)y * w, c);
+    o[6 + c] = diff(img, w, y, h, x, c);
+    o[9 + c] = sy * (diff(img, 1, x, w, (int64_t)y1 * w, c) - diff(img, 1, x, w, (int64_t)y0 * w, c));
+  }
+  float4* d = reinterpret_cast<float4*>(out + p * 12);
+  d[0] = make_float4(o[0], o[1], o[2], o[3]);
+  d[1] = make_float4(o[4], o[5], o[6], o[7]);
+  d[2] = make_float4(o[8], o[9], o[10], o[11]);
+}
+
+}  // namespace
+
+hipError_t launch_fd_slopes(const float* img, int32_t w, int32_t h, float* out, hipStream_t stream) {
+  const int64_t n = (int64_t)w * h;
+  fd_slopes_kernel<<<(unsigned)ceil_div(n, kThreads), kThreads, 0, stream>>>(img, w, h, out);
   return hipGetLastError();
 }
 

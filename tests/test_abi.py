@@ -123,6 +123,11 @@ def test_validation_rejects_bad_calls(L):
     assert lib.gs_upscale_hermite(F, 4, 5, ctypes.c_void_p(1 << 20), 3, 10, None) == L.GS_ERR_INVALID_ARGUMENT
     assert lib.gs_upscale_hermite(F, 4, 5, ctypes.c_void_p(4096 + 64), 8, 10, None) == L.GS_ERR_INVALID_ARGUMENT
     assert "overlap" in lib.gs_last_error_message().decode()
+    assert lib.gs_fd_slopes(F, 1, 5, ctypes.c_void_p(1 << 20), None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_fd_slopes(None, 4, 5, ctypes.c_void_p(1 << 20), None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_fd_slopes(F, 4, 5, ctypes.c_void_p((1 << 20) + 4), None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_fd_slopes(F, 4, 5, ctypes.c_void_p(4096 + 32), None) == L.GS_ERR_INVALID_ARGUMENT
+    assert "overlap" in lib.gs_last_error_message().decode()
 
 
 def test_binding_fails_loudly_without_library(L, monkeypatch):

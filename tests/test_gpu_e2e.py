@@ -108,8 +108,9 @@ def _full_size_case(torch, oracle, name, scale, samples_low, samples_hi, tile=16
     cam = scenes.workload_camera(name)
     cfg = scenes.render_config(sc["sh_degree"], tile_size=tile)
     w, h = cam["width"], cam["height"]
-    W, H = w * scale, h * scale
-    print(f"e2e {name} x{scale} tile={tile}: GPU", flush=True)
+    sx, sy = scale if isinstance(scale, tuple) else (scale, scale)
+    W, H = round(w * sx), round(h * sy)
+    print(f"e2e {name} x{scale} -> {W}x{H} tile={tile}: GPU", flush=True)
     rd = Renderer(sc)
     up, low = rd.render_upscaled(cam, cfg, W, H)
     torch.cuda.synchronize()
@@ -129,7 +130,8 @@ def _full_size_case(torch, oracle, name, scale, samples_low, samples_hi, tile=16
     assert_within(err, masked, max_masked_frac=1e-2)
     print(f"e2e {name}: oracle upscaled samples", flush=True)
     e_up, amb = _check_upscaled_samples(oracle, proj, order, cfg, (w, h), (W, H), up, samples_hi, 8)
-    report(f"e2e_{name}_x{scale}_upscaled_sampled", summarize(e_up, amb))
+    tag = f"{sx}x{sy}" if sx != sy else f"{sx}"
+    report(f"e2e_{name}_x{tag}_upscaled_sampled", summarize(e_up, amb))
     assert_within(e_up, amb, max_masked_frac=1e-2)
     return rd, cam, cfg, low, up
 
@@ -150,6 +152,12 @@ def test_e2e_scene_x4_full_size_sampled(torch_mod, oracle):
     plain = rd.render(cam, cfg, want_grads=False)
     torch.cuda.synchronize()
     assert np.array_equal(plain.cpu().numpy(), low[..., :3])
+
+
+@pytest.mark.parametrize("name,scale", [("clusters", 1.5), ("scene", 2.5), ("clusters", (4, 3)),
+                                        ("clusters", (2.25, 1.75))])
+def test_e2e_fractional_and_per_axis_scales(torch_mod, oracle, name, scale):
+    _full_size_case(torch_mod, oracle, name, scale, 120, 150)
 
 
 def test_tile_sizes_agree(torch_mod):

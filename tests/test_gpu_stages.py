@@ -305,3 +305,39 @@ def test_upscale_stage_small_and_identity(gs, oracle):
         np.testing.assert_allclose(out.cpu().numpy(), ref, atol=2e-5, rtol=0)
         if (w, h) == (W, H):
             np.testing.assert_allclose(out.cpu().numpy(), low[..., :3], atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# gs_fd_slopes (classical bicubic comparator) and its chain into the upscaler
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("w,h", [(2, 2), (3, 7), (128, 128), (257, 131), (960, 540)])
+def test_fd_slopes_stage(gs, oracle, w, h):
+    import torch
+    rng = np.random.default_rng(w * 1000 + h)
+    img = rng.uniform(0, 1, (h, w, 3)).astype(np.float32)
+    out = torch.full((h, w, 12), np.nan, dtype=torch.float32, device="cuda")
+    print(f"fd_slopes {w}x{h}", flush=True)
+    gs.gs_fd_slopes(_dev(img), out)
+    torch.cuda.synchronize()
+    ref = oracle.fd_slopes(img.astype(np.float64))
+    got = out.cpu().numpy()
+    np.testing.assert_array_equal(got[..., 0:3], img)
+    np.testing.assert_allclose(got, ref, atol=1e-6, rtol=0)
+
+
+def test_fd_bicubic_chain(gs, oracle, tiny_lowres):
+    """gs_fd_slopes then gs_upscale_hermite against the oracle's chain, at an
+    integer and two fractional factors."""
+    import torch
+    low = tiny_lowres
+    h, w = low.shape[:2]
+    slopes = torch.empty((h, w, 12), dtype=torch.float32, device="cuda")
+    gs.gs_fd_slopes(_dev(low[..., :3].copy()), slopes)
+    ref_slopes = oracle.fd_slopes(low[..., :3].astype(np.float64))
+    for (W, H) in [(4 * w, 4 * h), (int(2.5 * w), int(2.5 * h)), (3 * w // 2, 2 * h)]:
+        out = torch.full((H, W, 3), np.nan, dtype=torch.float32, device="cuda")
+        print(f"fd bicubic {w}x{h}->{W}x{H}", flush=True)
+        gs.gs_upscale_hermite(slopes, out)
+        torch.cuda.synchronize()
+        ref = oracle.upscale(ref_slopes, W, H)
+        np.testing.assert_allclose(out.cpu().numpy(), ref, atol=5e-6, rtol=0)
