@@ -60,6 +60,8 @@ WORKLOADS = {  # (scene, x factor, y factor); fractional and per-axis factors us
     "scene_x2.5": ("scene", 2.5, 2.5), "scene_x1.5": ("scene", 1.5, 1.5),
     "scene_x4_x3": ("scene", 4, 3),
     "clusters_x2": ("clusters", 2, 2), "tiny_x2": ("tiny", 2, 2),
+    # 1M Gaussians, 8 stereo pairs: 4 at 720x800 -> 1440x1600, 4 at 480x540 -> 1440x1620
+    "stereo16": ("batch", None, None),
 }
 
 
@@ -103,7 +105,7 @@ def run_gpu(args):
         b = rd.project(cam, cfg)
         if ev:
             ev[1].record()
-        rd.bin_sort(cam, cfg, b)
+        rd.bin_sort_async(cam, cfg, b)
         if ev:
             ev[2].record()
         rd.raster(cam, cfg, True, lo, b=b)
@@ -113,6 +115,10 @@ def run_gpu(args):
         if ev:
             ev[4].record()
 
+    # the pair count stays on the device: run until a frame fits the buffers
+    step(0)
+    while not rd.pairs_fit(cam, cfg):
+        step(0)
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
@@ -124,6 +130,7 @@ def run_gpu(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
+    assert rd.pairs_fit(cam, cfg), "pair count changed during the timed frames"
     stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])
     st_ms = stage.mean(0)
 
@@ -141,13 +148,16 @@ def run_gpu(args):
             b = rd.project(cam_hi, cfg_d)
             if ev:
                 ev[1].record()
-            rd.bin_sort(cam_hi, cfg_d, b)
+            rd.bin_sort_async(cam_hi, cfg_d, b)
             if ev:
                 ev[2].record()
             rd.raster(cam_hi, cfg_d, False, direct_out, b=b)
             if ev:
                 ev[3].record()
 
+        direct_step()
+        while not rd.pairs_fit(cam_hi, cfg_d):
+            direct_step()
         for _ in range(max(1, args.warmup)):
             direct_step()
         torch.cuda.synchronize()
@@ -157,6 +167,7 @@ def run_gpu(args):
             direct_step(devs[k])
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        assert rd.pairs_fit(cam_hi, cfg_d)
         st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in devs]).mean(0)
         rd._bufs.pop((W, H, tile), None)  # free this tile size's buffers
         return ms, st
@@ -232,6 +243,130 @@ def run_gpu(args):
         up_bytes=up_bytes, scene=sc, cam=cam)
 
 
+def run_batch(args):
+    """The batched stereo workload: autotuned setting, one captured graph per
+    frame for all 16 views; the direct baseline renders the 16 views at their
+    high-res sizes, also batched, graph-captured and tuned."""
+    import torch
+
+    from paper_2503_14171_amd import _lib as L
+    from paper_2503_14171_amd import autotune, scenes
+    from paper_2503_14171_amd.batch import ViewBatch
+    from paper_2503_14171_amd.render import Renderer
+
+    torch.cuda.set_device(0)
+    sc = scenes.workload_scene("batch")
+    cams, hi = scenes.stereo_rig()
+    cfg0 = scenes.render_config(sc["sh_degree"])
+    rd = Renderer(sc)
+    t0 = time.perf_counter()
+    tuned = autotune.tune(rd, cams, hi, cfg0, reps=5)
+    tuned_d = autotune.tune(rd, cams, hi, cfg0, reps=3, direct=True, tiles=(16, 32), batch_divs=(1, 2))
+    tune_s = time.perf_counter() - t0
+    cfg = dict(cfg0, tile_size=tuned["tile_size"], batch=tuned["batch"])
+    cfg_d = dict(cfg0, tile_size=tuned_d["tile_size"], batch=tuned_d["batch"])
+
+    def timed(vb, steps, warmup):
+        vb.capture()
+        vb.render()
+        for _ in range(warmup):
+            vb.launch()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            vb.launch()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t) / steps
+        assert vb.pairs_fit()
+        return ms
+
+    vb = ViewBatch(rd, cams, hi, cfg, band_rows=tuned["band_rows"])
+    ms = timed(vb, args.steps, args.warmup)
+    # per-stage times of the same chain, eager, with events between the calls
+    r = rd
+    ev = _events(torch, 5)
+    nrep = 5
+    acc = np.zeros(4)
+    for _ in range(nrep):
+        ev[0].record()
+        L.gs_project_views(r.means, r.log_scales, r.quats, r.opacity, r.sh, vb.cams, vb.cfg, vb.splats,
+                           vb.depth, vb.rect)
+        ev[1].record()
+        L.gs_bin_sort_views(r.n, vb.cams, vb.cfg, vb.depth, vb.rect, vb.capacity, vb.ids, vb.ranges,
+                            vb.n_pairs, vb.workspace)
+        ev[2].record()
+        L.gs_raster_grad_views(vb.splats, vb.ids, vb.ranges, vb.cams, vb.cfg, True, vb.low)
+        ev[3].record()
+        L.gs_upscale_hermite_views(vb.low, vb.lo, vb.up, vb.hi, vb.band_rows)
+        ev[4].record()
+        torch.cuda.synchronize()
+        acc += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    st = acc / nrep
+    nbl = torch.empty(sum(vb.lo_px), dtype=torch.int32, device="cuda")
+    L.gs_raster_grad_views(vb.splats, vb.ids, vb.ranges, vb.cams, vb.cfg, True, vb.low, nbl)
+    frags = int(nbl.sum().item())
+    pairs = int(vb.n_pairs.item())
+    up_imgs = [u.clone() for u in vb.views()[1]]
+    del vb, nbl
+    vd = ViewBatch(rd, cams, hi, cfg_d, direct=True)
+    ms_d = timed(vd, max(3, args.steps // 2), 1)
+    psnrs = [_psnr(u.clamp(0, 1), d.clamp(0, 1)) for u, d in zip(up_imgs, vd.views()[1])]
+    pairs_d = int(vd.n_pairs.item())
+    del vd
+    out_px = sum(W * H for (W, H) in hi)
+    lo_px = sum(c["width"] * c["height"] for c in cams)
+    up_bytes = lo_px * UPSCALE_BYTES_LO + out_px * UPSCALE_BYTES_HI
+    return dict(name="batch", n=rd.n, cams=cams, hi=hi, cfg=cfg, tuned=tuned, tuned_direct=tuned_d,
+                tune_s=tune_s, ms_step=ms, value=out_px / (ms * 1e-3) / 1e6,
+                stages_ms=dict(project=st[0], bin_sort=st[1], raster_grad=st[2], upscale=st[3]),
+                direct=dict(value=out_px / (ms_d * 1e-3) / 1e6, ms_per_frame=ms_d, pairs=pairs_d),
+                psnr=float(np.mean(psnrs)), psnr_min=float(np.min(psnrs)), frags=frags, pairs=pairs,
+                achieved_tflops=frags * FLOP_PER_BLEND[True] / (st[2] * 1e-3) / 1e12,
+                up_gbs=up_bytes / (st[3] * 1e-3) / 1e9, up_bytes=up_bytes, out_px=out_px)
+
+
+def batch_line(args, res):
+    tuned = res["tuned"]
+    return {
+        "metric": METRIC,
+        "value": round(res["value"], 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch: {res['n']} Gaussians, SH degree 3, 8 stereo pairs (16 views): "
+                               "4 pairs 720x800 -> 1440x1600 (x2), 4 pairs 480x540 -> 1440x1620 (x3); "
+                               "one HIP graph per frame",
+                   "gaussians": res["n"], "views": len(res["cams"]), "output_pixels": res["out_px"],
+                   "tuned": {k: tuned[k] for k in ("tile_size", "batch", "band_rows")},
+                   "tuned_direct": {k: res["tuned_direct"][k] for k in ("tile_size", "batch")}},
+        "roofline": {"kernel": "gs_raster_grad_views", "bound": "alu",
+                     "achieved": round(res["achieved_tflops"], 3), "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(res["achieved_tflops"] / FP32_VALU_TFLOPS, 4), "traffic": None,
+                     "units": f"{res['frags']} blended fragments x {FLOP_PER_BLEND[True]} FLOP"},
+        "upscaler_roofline": {"kernel": "gs_upscale_hermite_views", "bound": "hbm",
+                              "achieved": round(res["up_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(res["up_gbs"] / HBM_PEAK_GBS, 4), "bytes": res["up_bytes"],
+                              "traffic": None},
+        "stages_ms": {k: round(v, 4) for k, v in res["stages_ms"].items()},
+        "direct": {"value": round(res["direct"]["value"], 2), "unit": "Mpix/s",
+                   "ms_per_frame": round(res["direct"]["ms_per_frame"], 4)},
+        "speedup_vs_direct": round(res["value"] / res["direct"]["value"], 3),
+        "psnr_vs_direct_db": round(res["psnr"], 2),
+        "psnr_vs_direct_min_db": round(res["psnr_min"], 2),
+        "pairs": {"lowres": res["pairs"], "direct": res["direct"]["pairs"]},
+        "autotune_s": round(res["tune_s"], 1),
+        "autotune_trials": [{k: (round(v, 4) if k == "ms" else v) for k, v in t.items()}
+                            for t in tuned["trials"]],
+    }
+
+
 def cpu_baseline(res, budget_s):
     """The FP64 oracle on a bounded sample of the same frame: projection and
     depth order of every Gaussian, compositing of a random sample of low-res
@@ -286,6 +421,10 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if WORKLOADS[args.workload][0] == "batch":
+        res = run_batch(args)
+        print(json.dumps(batch_line(args, res)), flush=True)
+        return
     res = run_gpu(args)
     if args.copy_probe_mb:
         import torch

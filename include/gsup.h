@@ -22,7 +22,9 @@
  *     (n_pairs) live in HOST memory.
  *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *     Every call only enqueues work on that stream and returns, except
- *     gs_bin_sort, which waits on the stream once to read the pair count.
+ *     gs_bin_sort, which waits on the stream once to read the pair count
+ *     (gs_bin_sort_async and gs_bin_sort_views do not wait: the chains they
+ *     belong to can be captured in a HIP graph).
  *   - Arguments are validated on the host before anything is enqueued.  On
  *     any error the call returns a non-zero gs_status, enqueues nothing (or
  *     nothing further), and gs_last_error_message() describes the problem.
@@ -41,6 +43,9 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Most camera views one batched call takes. */
+#define GS_MAX_VIEWS 16
 
 typedef enum gs_status {
   GS_OK = 0,
@@ -71,6 +76,8 @@ typedef struct gs_raster_cfg {
   float alpha_max;   /* alpha > alpha_max is clamped to alpha_max (zero screen derivatives), < 1 */
   float t_min;       /* a pixel stops once its transmittance after a blend is < t_min, in (0, 1) */
   float bg[3];       /* background colour behind the last fragment */
+  int32_t batch;     /* splats staged per LDS batch in the rasterizer: 0 or tile_size^2 (one per
+                        thread), tile_size^2 / 2 or tile_size^2 / 4; changes only the speed */
 } gs_raster_cfg;
 
 /* A projected Gaussian (48 bytes, 16-byte aligned).  The 2D mean is kept in
@@ -140,6 +147,18 @@ gs_status gs_bin_sort(int64_t n, const float* depth, const int32_t* rect, const 
                       int32_t* tile_ranges, int64_t* n_pairs, void* workspace,
                       size_t workspace_bytes, void* stream);
 
+/* gs_bin_sort_async -- gs_bin_sort without the wait: the pair count K is
+ * written to n_pairs_dev (DEVICE, one int64, 8-byte aligned) on the stream.
+ * When K > capacity (or K >= 2^31) nothing is emitted, every tile range is
+ * [0, 0) and sorted_ids is left as it was: the caller reads *n_pairs_dev
+ * after the stream has run, grows the buffers and runs the frame again.
+ * Never waits on the stream; safe to capture in a HIP graph.  Same inputs,
+ * outputs and workspace as gs_bin_sort. */
+gs_status gs_bin_sort_async(int64_t n, const float* depth, const int32_t* rect,
+                            const gs_camera* cam, const gs_raster_cfg* cfg, int64_t capacity,
+                            int32_t* sorted_ids, int32_t* tile_ranges, int64_t* n_pairs_dev,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
 /* gs_raster_grad -- front-to-back alpha blending of every pixel's tile list,
  * with the analytical screen-space derivatives of the blended colour.
  * Follows Sec. "Image Gradient Based Upscaling" (3DGS image gradients: the
@@ -186,6 +205,57 @@ gs_status gs_upscale_hermite(const float* in, int32_t w, int32_t h, float* out, 
  * overlap): values, f_x = (f[x+1] - f[x-1]) / 2, f_y likewise, f_xy = the
  * y-difference of f_x; one-sided differences on the border rows/columns. */
 gs_status gs_fd_slopes(const float* img, int32_t w, int32_t h, float* out, void* stream);
+
+/* ---- Batched views --------------------------------------------------------
+ * Many cameras of one scene (stereo pairs, training batches) go through the
+ * same four steps with one launch per step.  `cams` is a HOST array of
+ * n_views (1..GS_MAX_VIEWS) cameras; per-view device arrays are concatenated
+ * in view order.  Each view's results equal those of the single-view calls
+ * for that camera.  None of these calls waits on the stream. */
+
+/* Tiles of all views: sum over v of gs_num_tiles(cams[v].width, cams[v].height, tile_size). */
+int64_t gs_num_tiles_views(int32_t n_views, const gs_camera* cams, int32_t tile_size);
+
+/* gs_project_views -- gs_project for every view, reading each Gaussian's
+ * parameters once per batch.  Outputs splats [n_views, n], depth [n_views, n],
+ * rect [n_views, n, 4]: record v * n + i is Gaussian i seen by view v, its
+ * rect in view v's tile grid.  n * n_views < 2^31. */
+gs_status gs_project_views(int64_t n, const float* means, const float* log_scales,
+                           const float* quats, const float* opacity, const float* sh,
+                           int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                           gs_splat* splats, float* depth, int32_t* rect, void* stream);
+
+/* Bytes of device workspace gs_bin_sort_views needs. */
+size_t gs_bin_sort_views_workspace_size(int64_t n, int32_t n_views, const gs_camera* cams,
+                                        const gs_raster_cfg* cfg, int64_t capacity);
+
+/* gs_bin_sort_views -- per-tile lists of all views at once.  Tiles are
+ * numbered view after view (view v's tile (tx, ty) has the id
+ * sum_{u<v} tiles(u) + ty * tiles_x(v) + tx); tile_ranges [T_all, 2]; list
+ * entries are splat records v * n + i, ordered by (FP32 depth, i).  The pair
+ * count goes to n_pairs_dev as in gs_bin_sort_async (same overflow rule). */
+gs_status gs_bin_sort_views(int64_t n, int32_t n_views, const gs_camera* cams,
+                            const gs_raster_cfg* cfg, const float* depth, const int32_t* rect,
+                            int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
+                            int64_t* n_pairs_dev, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/* gs_raster_grad_views -- one launch over the tiles of all views.  out holds
+ * the views' [H_v, W_v, 12] (or [H_v, W_v, 3]) images back to back; n_blend
+ * (optional) their [H_v, W_v] counts. */
+gs_status gs_raster_grad_views(const gs_splat* splats, const int32_t* sorted_ids,
+                               const int32_t* tile_ranges, int32_t n_views,
+                               const gs_camera* cams, const gs_raster_cfg* cfg,
+                               int32_t want_grads, float* out, int32_t* n_blend, void* stream);
+
+/* gs_upscale_hermite_views -- one launch for all views.  lo_sizes and
+ * hi_sizes are HOST arrays [n_views][2] of (width, height); in holds the
+ * views' [h_v, w_v, 12] buffers back to back, out their [H_v, W_v, 3] images.
+ * band_rows: output rows per workgroup, 4, 8, 16 or 32 (0 = 16); it changes
+ * only the speed. */
+gs_status gs_upscale_hermite_views(const float* in, int32_t n_views, const int32_t* lo_sizes,
+                                   float* out, const int32_t* hi_sizes, int32_t band_rows,
+                                   void* stream);
 
 /* Message of the last failed call on this host thread ("" if none). */
 const char* gs_last_error_message(void);

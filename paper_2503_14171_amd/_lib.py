@@ -42,7 +42,7 @@ class GsRasterCfg(ctypes.Structure):
     _fields_ = [("tile_size", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
                 ("dilation", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
-                ("bg", ctypes.c_float * 3)]
+                ("bg", ctypes.c_float * 3), ("batch", ctypes.c_int32)]
 
 
 _lib = None
@@ -70,6 +70,21 @@ def lib() -> ctypes.CDLL:
         L.gs_raster_grad.restype = ctypes.c_int
         L.gs_upscale_hermite.argtypes = [P, i32, i32, P, i32, i32, P]
         L.gs_upscale_hermite.restype = ctypes.c_int
+        cams_p = ctypes.POINTER(GsCamera)
+        L.gs_bin_sort_async.argtypes = [i64, P, P, cam_p, cfg_p, i64, P, P, P, P, sz, P]
+        L.gs_bin_sort_async.restype = ctypes.c_int
+        L.gs_num_tiles_views.argtypes = [i32, cams_p, i32]
+        L.gs_num_tiles_views.restype = i64
+        L.gs_project_views.argtypes = [i64, P, P, P, P, P, i32, cams_p, cfg_p, P, P, P, P]
+        L.gs_project_views.restype = ctypes.c_int
+        L.gs_bin_sort_views_workspace_size.argtypes = [i64, i32, cams_p, cfg_p, i64]
+        L.gs_bin_sort_views_workspace_size.restype = sz
+        L.gs_bin_sort_views.argtypes = [i64, i32, cams_p, cfg_p, P, P, i64, P, P, P, P, sz, P]
+        L.gs_bin_sort_views.restype = ctypes.c_int
+        L.gs_raster_grad_views.argtypes = [P, P, P, i32, cams_p, cfg_p, i32, P, P, P]
+        L.gs_raster_grad_views.restype = ctypes.c_int
+        L.gs_upscale_hermite_views.argtypes = [P, i32, ctypes.POINTER(i32), P, ctypes.POINTER(i32), i32, P]
+        L.gs_upscale_hermite_views.restype = ctypes.c_int
         L.gs_fd_slopes.argtypes = [P, i32, i32, P, P]
         L.gs_fd_slopes.restype = ctypes.c_int
         L.gs_last_error_message.restype = ctypes.c_char_p
@@ -95,7 +110,16 @@ def raster_cfg(cfg: dict) -> GsRasterCfg:
     c.dilation = float(cfg["dilation"])
     c.alpha_min, c.alpha_max, c.t_min = float(cfg["alpha_min"]), float(cfg["alpha_max"]), float(cfg["t_min"])
     c.bg[:] = [float(v) for v in cfg["bg"]]
+    c.batch = int(cfg.get("batch", 0))
     return c
+
+
+def cameras(cams) -> ctypes.Array:
+    """Host array of gs_camera for the batched calls."""
+    arr = (GsCamera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k] = camera(c)
+    return arr
 
 
 def _ptr(t: torch.Tensor | None, dtype=None):
@@ -182,3 +206,59 @@ def gs_fd_slopes(img, out, stream=None) -> None:
     if img.shape[2] != 3 or tuple(out.shape) != (h, w, 12):
         raise ValueError("img must be [h, w, 3] and out [h, w, 12]")
     _check(lib().gs_fd_slopes(_ptr(img, torch.float32), w, h, _ptr(out, torch.float32), _stream(stream)))
+
+
+def gs_bin_sort_async(n: int, depth, rect, cam: dict, cfg: dict, capacity: int, sorted_ids, tile_ranges,
+                      n_pairs_dev, workspace, stream=None) -> None:
+    """gs_bin_sort without the wait; the pair count lands in n_pairs_dev (int64 [1])."""
+    _check(lib().gs_bin_sort_async(n, _ptr(depth, torch.float32), _ptr(rect, torch.int32),
+                                   ctypes.byref(camera(cam)), ctypes.byref(raster_cfg(cfg)), capacity,
+                                   _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
+                                   _ptr(n_pairs_dev, torch.int64), _ptr(workspace, torch.uint8),
+                                   workspace.numel(), _stream(stream)))
+
+
+# ---- batched views ---------------------------------------------------------
+def gs_num_tiles_views(cams, tile_size: int) -> int:
+    return int(lib().gs_num_tiles_views(len(cams), cameras(cams), tile_size))
+
+
+def gs_project_views(means, log_scales, quats, opacity, sh, cams, cfg: dict, splats, depth, rect,
+                     stream=None) -> None:
+    """splats [V*n, 12], depth [V*n], rect [V*n, 4]; record v*n+i = Gaussian i in view v."""
+    n = means.shape[0]
+    f = torch.float32
+    _check(lib().gs_project_views(n, _ptr(means, f), _ptr(log_scales, f), _ptr(quats, f), _ptr(opacity, f),
+                                  _ptr(sh, f), len(cams), cameras(cams), ctypes.byref(raster_cfg(cfg)),
+                                  _ptr(splats, f), _ptr(depth, f), _ptr(rect, torch.int32), _stream(stream)))
+
+
+def gs_bin_sort_views_workspace_size(n: int, cams, cfg: dict, capacity: int) -> int:
+    return int(lib().gs_bin_sort_views_workspace_size(n, len(cams), cameras(cams),
+                                                      ctypes.byref(raster_cfg(cfg)), capacity))
+
+
+def gs_bin_sort_views(n: int, cams, cfg: dict, depth, rect, capacity: int, sorted_ids, tile_ranges,
+                      n_pairs_dev, workspace, stream=None) -> None:
+    _check(lib().gs_bin_sort_views(n, len(cams), cameras(cams), ctypes.byref(raster_cfg(cfg)),
+                                   _ptr(depth, torch.float32), _ptr(rect, torch.int32), capacity,
+                                   _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
+                                   _ptr(n_pairs_dev, torch.int64), _ptr(workspace, torch.uint8),
+                                   workspace.numel(), _stream(stream)))
+
+
+def gs_raster_grad_views(splats, sorted_ids, tile_ranges, cams, cfg: dict, want_grads: bool, out,
+                         n_blend=None, stream=None) -> None:
+    _check(lib().gs_raster_grad_views(_ptr(splats, torch.float32), _ptr(sorted_ids, torch.int32),
+                                      _ptr(tile_ranges, torch.int32), len(cams), cameras(cams),
+                                      ctypes.byref(raster_cfg(cfg)), 1 if want_grads else 0,
+                                      _ptr(out, torch.float32), _ptr(n_blend, torch.int32), _stream(stream)))
+
+
+def gs_upscale_hermite_views(inp, lo_sizes, out, hi_sizes, band_rows: int = 0, stream=None) -> None:
+    """inp: the views' [h, w, 12] buffers back to back; sizes: lists of (width, height)."""
+    nv = len(lo_sizes)
+    lo = (ctypes.c_int32 * (2 * nv))(*[int(v) for wh in lo_sizes for v in wh])
+    hi = (ctypes.c_int32 * (2 * nv))(*[int(v) for wh in hi_sizes for v in wh])
+    _check(lib().gs_upscale_hermite_views(_ptr(inp, torch.float32), nv, lo, _ptr(out, torch.float32), hi,
+                                          band_rows, _stream(stream)))

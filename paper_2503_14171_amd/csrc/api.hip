@@ -9,6 +9,12 @@
 
 namespace gsup {
 
+#define GS_CHECK_INNER(x)        \
+  do {                           \
+    const gs_status s_ = (x);    \
+    if (s_ != GS_OK) return s_;  \
+  } while (0)
+
 namespace {
 thread_local char g_msg[1024] = "";
 
@@ -53,7 +59,31 @@ gs_status check_cfg(const char* fn, const gs_raster_cfg* cfg) {
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: need 0 < t_min < 1 (got %g)", fn, cfg->t_min);
   for (int k = 0; k < 3; ++k)
     if (!finite(cfg->bg[k])) return fail(GS_ERR_INVALID_ARGUMENT, "%s: bg not finite", fn);
+  const int32_t nt = cfg->tile_size * cfg->tile_size;
+  if (cfg->batch != 0 && cfg->batch != nt && cfg->batch != nt / 2 && cfg->batch != nt / 4)
+    return fail(GS_ERR_UNSUPPORTED, "%s: batch %d (supported: 0, %d, %d, %d)", fn, cfg->batch, nt,
+                nt / 2, nt / 4);
   return GS_OK;
+}
+
+gs_status check_views(const char* fn, int32_t nv, const gs_camera* cams) {
+  if (nv < 1 || nv > GS_MAX_VIEWS)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n_views %d outside [1, %d]", fn, nv, GS_MAX_VIEWS);
+  if (!cams) return fail(GS_ERR_INVALID_ARGUMENT, "%s: cams is NULL", fn);
+  for (int v = 0; v < nv; ++v) GS_CHECK_INNER(check_camera(fn, cams + v));
+  return GS_OK;
+}
+
+int64_t total_tiles(int32_t nv, const gs_camera* cams, int32_t tile) {
+  int64_t t = 0;
+  for (int v = 0; v < nv; ++v) t += ceil_div(cams[v].width, tile) * ceil_div(cams[v].height, tile);
+  return t;
+}
+
+int64_t total_pixels(int32_t nv, const gs_camera* cams) {
+  int64_t t = 0;
+  for (int v = 0; v < nv; ++v) t += (int64_t)cams[v].width * cams[v].height;
+  return t;
 }
 
 }  // namespace
@@ -88,6 +118,125 @@ using namespace gsup;
     if (s_ != GS_OK) return s_;  \
   } while (0)
 
+namespace {
+
+gs_status project_impl(const char* fn, int64_t n, const float* means, const float* log_scales,
+                       const float* quats, const float* opacity, const float* sh, int32_t nv,
+                       const gs_camera* cams, const gs_raster_cfg* cfg, gs_splat* splats,
+                       float* depth, int32_t* rect, void* stream) {
+  GS_CHECK(check_views(fn, nv, cams));
+  GS_CHECK(check_cfg(fn, cfg));
+  if (n < 0 || n * nv >= (int64_t(1) << 31))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n * n_views = %lld * %d outside [0, 2^31)", fn,
+                (long long)n, nv);
+  if (n == 0) return GS_OK;
+  if (!means || !log_scales || !quats || !opacity || !sh || !splats || !depth || !rect)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL array argument", fn);
+  if (!aligned(quats, 16) || !aligned(sh, 16) || !aligned(splats, 16) || !aligned(rect, 16) ||
+      !aligned(means, 4) || !aligned(log_scales, 4) || !aligned(opacity, 4) || !aligned(depth, 4))
+    return fail(GS_ERR_INVALID_ARGUMENT,
+                "%s: quats, sh, splats and rect must be 16-byte aligned (others 4-byte)", fn);
+  return check_hip(launch_project(n, means, log_scales, quats, opacity, sh, nv, cams, *cfg, splats,
+                                  depth, rect, static_cast<hipStream_t>(stream)),
+                   "projection launch");
+}
+
+size_t bin_sort_ws(int64_t n, int32_t nv, const gs_camera* cams, const gs_raster_cfg* cfg,
+                   int64_t capacity) {
+  if (!cams || !cfg || nv < 1 || nv > GS_MAX_VIEWS || n < 0 || capacity < 0 ||
+      (cfg->tile_size != 8 && cfg->tile_size != 16 && cfg->tile_size != 32))
+    return 0;
+  for (int v = 0; v < nv; ++v)
+    if (cams[v].width < 1 || cams[v].height < 1) return 0;
+  return make_bin_sort_plan(n * nv, capacity, total_tiles(nv, cams, cfg->tile_size)).bytes;
+}
+
+gs_status bin_sort_impl(const char* fn, int64_t n, int32_t nv, const gs_camera* cams,
+                        const gs_raster_cfg* cfg, const float* depth, const int32_t* rect,
+                        int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
+                        int64_t* n_pairs, int64_t* n_pairs_dev, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+  GS_CHECK(check_views(fn, nv, cams));
+  GS_CHECK(check_cfg(fn, cfg));
+  if (n < 0 || n * nv >= (int64_t(1) << 31))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n * n_views = %lld * %d outside [0, 2^31)", fn,
+                (long long)n, nv);
+  if (capacity < 0 || capacity >= (int64_t(1) << 31))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: capacity %lld outside [0, 2^31)", fn,
+                (long long)capacity);
+  if ((!n_pairs && !n_pairs_dev) || !tile_ranges || !workspace || (n > 0 && (!depth || !rect)) ||
+      (capacity > 0 && !sorted_ids))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
+  if ((n > 0 && !aligned(rect, 16)) || !aligned(workspace, 256) || !aligned(tile_ranges, 8) ||
+      (n_pairs_dev && !aligned(n_pairs_dev, 8)))
+    return fail(GS_ERR_INVALID_ARGUMENT,
+                "%s: rect must be 16-byte, tile_ranges and n_pairs 8-byte, workspace 256-byte "
+                "aligned", fn);
+  const int64_t tiles = total_tiles(nv, cams, cfg->tile_size);
+  if (tiles >= (int64_t(1) << 31))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: %lld tiles exceed 2^31", fn, (long long)tiles);
+  const BinSortPlan plan = make_bin_sort_plan(n * nv, capacity, tiles);
+  if (workspace_bytes < plan.bytes)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: workspace of %zu bytes, %zu needed", fn,
+                workspace_bytes, plan.bytes);
+  const ViewTiles vt = make_view_tiles(nv, cams, cfg->tile_size, n);
+  return run_bin_sort(plan, vt, depth, rect, sorted_ids, tile_ranges, n_pairs, n_pairs_dev,
+                      workspace, static_cast<hipStream_t>(stream));
+}
+
+gs_status raster_impl(const char* fn, const gs_splat* splats, const int32_t* sorted_ids,
+                      const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,
+                      const gs_raster_cfg* cfg, int32_t want_grads, float* out, int32_t* n_blend,
+                      void* stream) {
+  GS_CHECK(check_views(fn, nv, cams));
+  GS_CHECK(check_cfg(fn, cfg));
+  if (!splats || !sorted_ids || !tile_ranges || !out)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
+  if (!aligned(splats, 16) || !aligned(tile_ranges, 8) || !aligned(out, want_grads ? 16 : 4) ||
+      !aligned(sorted_ids, 4) || (n_blend && !aligned(n_blend, 4)))
+    return fail(GS_ERR_INVALID_ARGUMENT,
+                "%s: splats (and out with gradients) must be 16-byte aligned", fn);
+  if (total_tiles(nv, cams, cfg->tile_size) >= (int64_t(1) << 31))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: too many tiles", fn);
+  return check_hip(launch_raster(splats, sorted_ids, tile_ranges, nv, cams, *cfg, want_grads != 0,
+                                 out, n_blend, static_cast<hipStream_t>(stream)),
+                   "raster launch");
+}
+
+gs_status upscale_impl(const char* fn, const float* in, int32_t nv, const int32_t* lo,
+                       float* out, const int32_t* hi, int32_t band_rows, void* stream) {
+  if (!in || !out || !lo || !hi) return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
+  if (nv < 1 || nv > GS_MAX_VIEWS)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n_views %d outside [1, %d]", fn, nv, GS_MAX_VIEWS);
+  if (band_rows != 0 && band_rows != 4 && band_rows != 8 && band_rows != 16 && band_rows != 32)
+    return fail(GS_ERR_UNSUPPORTED, "%s: band_rows %d (supported: 0, 4, 8, 16, 32)", fn,
+                band_rows);
+  int64_t in_px = 0, out_px = 0;
+  for (int v = 0; v < nv; ++v) {
+    const int32_t w = lo[2 * v], h = lo[2 * v + 1], W = hi[2 * v], H = hi[2 * v + 1];
+    if (w < 2 || h < 2 || w > kMaxSide || h > kMaxSide)
+      return fail(GS_ERR_INVALID_ARGUMENT, "%s: low-res %d x %d outside [2, %d]", fn, w, h,
+                  kMaxSide);
+    if (W < w || H < h || W > 4 * kMaxSide || H > 4 * kMaxSide)
+      return fail(GS_ERR_INVALID_ARGUMENT,
+                  "%s: high-res %d x %d must be >= low-res %d x %d and <= %d", fn, W, H, w, h,
+                  4 * kMaxSide);
+    in_px += (int64_t)w * h;
+    out_px += (int64_t)W * H;
+  }
+  if (!aligned(in, 16) || !aligned(out, 4))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: in must be 16-byte aligned", fn);
+  const char* ib = reinterpret_cast<const char*>(in);
+  const char* ie = ib + (size_t)in_px * 12 * sizeof(float);
+  const char* ob = reinterpret_cast<const char*>(out);
+  const char* oe = ob + (size_t)out_px * 3 * sizeof(float);
+  if (ib < oe && ob < ie) return fail(GS_ERR_INVALID_ARGUMENT, "%s: in and out overlap", fn);
+  return check_hip(launch_upscale(in, nv, lo, out, hi, band_rows, static_cast<hipStream_t>(stream)),
+                   "upscale launch");
+}
+
+}  // namespace
+
 extern "C" {
 
 int64_t gs_num_tiles(int32_t width, int32_t height, int32_t tile_size) {
@@ -99,34 +248,19 @@ const char* gs_last_error_message(void) { return g_msg; }
 
 const char* gs_version(void) { return "gsup 0.1 (gfx950)"; }
 
+
 gs_status gs_project(int64_t n, const float* means, const float* log_scales, const float* quats,
                      const float* opacity, const float* sh, const gs_camera* cam,
                      const gs_raster_cfg* cfg, gs_splat* splats, float* depth, int32_t* rect,
                      void* stream) {
   g_msg[0] = 0;
-  const char* fn = "gs_project";
-  GS_CHECK(check_camera(fn, cam));
-  GS_CHECK(check_cfg(fn, cfg));
-  if (n < 0 || n >= (int64_t(1) << 31))
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n = %lld outside [0, 2^31)", fn, (long long)n);
-  if (n == 0) return GS_OK;
-  if (!means || !log_scales || !quats || !opacity || !sh || !splats || !depth || !rect)
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL array argument", fn);
-  if (!aligned(quats, 16) || !aligned(sh, 16) || !aligned(splats, 16) || !aligned(rect, 16) ||
-      !aligned(means, 4) || !aligned(log_scales, 4) || !aligned(opacity, 4) || !aligned(depth, 4))
-    return fail(GS_ERR_INVALID_ARGUMENT,
-                "%s: quats, sh, splats and rect must be 16-byte aligned (others 4-byte)", fn);
-  return check_hip(launch_project(n, means, log_scales, quats, opacity, sh, *cam, *cfg, splats,
-                                  depth, rect, static_cast<hipStream_t>(stream)),
-                   "gs_project launch");
+  return project_impl("gs_project", n, means, log_scales, quats, opacity, sh, 1, cam, cfg, splats,
+                      depth, rect, stream);
 }
 
 size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* cam,
                                   const gs_raster_cfg* cfg) {
-  if (!cam || !cfg || n < 0 || capacity < 0 || cam->width < 1 || cam->height < 1 ||
-      (cfg->tile_size != 8 && cfg->tile_size != 16 && cfg->tile_size != 32))
-    return 0;
-  return make_bin_sort_plan(n, capacity, cam->width, cam->height, cfg->tile_size).bytes;
+  return bin_sort_ws(n, 1, cam, cfg, capacity);
 }
 
 gs_status gs_bin_sort(int64_t n, const float* depth, const int32_t* rect, const gs_camera* cam,
@@ -134,26 +268,19 @@ gs_status gs_bin_sort(int64_t n, const float* depth, const int32_t* rect, const 
                       int32_t* tile_ranges, int64_t* n_pairs, void* workspace,
                       size_t workspace_bytes, void* stream) {
   g_msg[0] = 0;
-  const char* fn = "gs_bin_sort";
-  GS_CHECK(check_camera(fn, cam));
-  GS_CHECK(check_cfg(fn, cfg));
-  if (n < 0 || n >= (int64_t(1) << 31))
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n = %lld outside [0, 2^31)", fn, (long long)n);
-  if (capacity < 0 || capacity >= (int64_t(1) << 31))
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: capacity %lld outside [0, 2^31)", fn,
-                (long long)capacity);
-  if (!n_pairs || !tile_ranges || !workspace || (n > 0 && (!depth || !rect)) ||
-      (capacity > 0 && !sorted_ids))
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
-  if ((n > 0 && !aligned(rect, 16)) || !aligned(workspace, 256) || !aligned(tile_ranges, 8))
-    return fail(GS_ERR_INVALID_ARGUMENT,
-                "%s: rect must be 16-byte, tile_ranges 8-byte, workspace 256-byte aligned", fn);
-  const BinSortPlan plan = make_bin_sort_plan(n, capacity, cam->width, cam->height, cfg->tile_size);
-  if (workspace_bytes < plan.bytes)
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: workspace of %zu bytes, %zu needed", fn,
-                workspace_bytes, plan.bytes);
-  return run_bin_sort(plan, depth, rect, sorted_ids, tile_ranges, n_pairs, workspace,
-                      static_cast<hipStream_t>(stream));
+  if (!n_pairs) return fail(GS_ERR_INVALID_ARGUMENT, "gs_bin_sort: n_pairs is NULL");
+  return bin_sort_impl("gs_bin_sort", n, 1, cam, cfg, depth, rect, capacity, sorted_ids,
+                       tile_ranges, n_pairs, nullptr, workspace, workspace_bytes, stream);
+}
+
+gs_status gs_bin_sort_async(int64_t n, const float* depth, const int32_t* rect,
+                            const gs_camera* cam, const gs_raster_cfg* cfg, int64_t capacity,
+                            int32_t* sorted_ids, int32_t* tile_ranges, int64_t* n_pairs_dev,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  g_msg[0] = 0;
+  if (!n_pairs_dev) return fail(GS_ERR_INVALID_ARGUMENT, "gs_bin_sort_async: n_pairs_dev is NULL");
+  return bin_sort_impl("gs_bin_sort_async", n, 1, cam, cfg, depth, rect, capacity, sorted_ids,
+                       tile_ranges, nullptr, n_pairs_dev, workspace, workspace_bytes, stream);
 }
 
 gs_status gs_raster_grad(const gs_splat* splats, const int32_t* sorted_ids,
@@ -161,40 +288,65 @@ gs_status gs_raster_grad(const gs_splat* splats, const int32_t* sorted_ids,
                          const gs_raster_cfg* cfg, int32_t want_grads, float* out,
                          int32_t* n_blend, void* stream) {
   g_msg[0] = 0;
-  const char* fn = "gs_raster_grad";
-  GS_CHECK(check_camera(fn, cam));
-  GS_CHECK(check_cfg(fn, cfg));
-  if (!splats || !sorted_ids || !tile_ranges || !out)
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
-  if (!aligned(splats, 16) || !aligned(tile_ranges, 8) || !aligned(out, want_grads ? 16 : 4) ||
-      !aligned(sorted_ids, 4) || (n_blend && !aligned(n_blend, 4)))
-    return fail(GS_ERR_INVALID_ARGUMENT,
-                "%s: splats (and out with gradients) must be 16-byte aligned", fn);
-  return check_hip(launch_raster(splats, sorted_ids, tile_ranges, *cam, *cfg, want_grads != 0, out,
-                                 n_blend, static_cast<hipStream_t>(stream)),
-                   "gs_raster_grad launch");
+  return raster_impl("gs_raster_grad", splats, sorted_ids, tile_ranges, 1, cam, cfg, want_grads,
+                     out, n_blend, stream);
 }
 
 gs_status gs_upscale_hermite(const float* in, int32_t w, int32_t h, float* out, int32_t W,
                              int32_t H, void* stream) {
   g_msg[0] = 0;
-  const char* fn = "gs_upscale_hermite";
-  if (!in || !out) return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
-  if (w < 2 || h < 2 || w > kMaxSide || h > kMaxSide)
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: low-res %d x %d outside [2, %d]", fn, w, h, kMaxSide);
-  if (W < w || H < h || W > 4 * kMaxSide || H > 4 * kMaxSide)
-    return fail(GS_ERR_INVALID_ARGUMENT,
-                "%s: high-res %d x %d must be >= low-res %d x %d and <= %d", fn, W, H, w, h,
-                4 * kMaxSide);
-  if (!aligned(in, 16) || !aligned(out, 4))
-    return fail(GS_ERR_INVALID_ARGUMENT, "%s: in must be 16-byte aligned", fn);
-  const char* ib = reinterpret_cast<const char*>(in);
-  const char* ie = ib + (size_t)w * h * 12 * sizeof(float);
-  const char* ob = reinterpret_cast<const char*>(out);
-  const char* oe = ob + (size_t)W * H * 3 * sizeof(float);
-  if (ib < oe && ob < ie) return fail(GS_ERR_INVALID_ARGUMENT, "%s: in and out overlap", fn);
-  return check_hip(launch_upscale(in, w, h, out, W, H, static_cast<hipStream_t>(stream)),
-                   "gs_upscale_hermite launch");
+  const int32_t lo[2] = {w, h}, hi[2] = {W, H};
+  return upscale_impl("gs_upscale_hermite", in, 1, lo, out, hi, 0, stream);
+}
+
+int64_t gs_num_tiles_views(int32_t n_views, const gs_camera* cams, int32_t tile_size) {
+  if (n_views < 1 || n_views > GS_MAX_VIEWS || !cams || tile_size < 1) return 0;
+  for (int v = 0; v < n_views; ++v)
+    if (cams[v].width < 1 || cams[v].height < 1) return 0;
+  return total_tiles(n_views, cams, tile_size);
+}
+
+gs_status gs_project_views(int64_t n, const float* means, const float* log_scales,
+                           const float* quats, const float* opacity, const float* sh,
+                           int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                           gs_splat* splats, float* depth, int32_t* rect, void* stream) {
+  g_msg[0] = 0;
+  return project_impl("gs_project_views", n, means, log_scales, quats, opacity, sh, n_views, cams,
+                      cfg, splats, depth, rect, stream);
+}
+
+size_t gs_bin_sort_views_workspace_size(int64_t n, int32_t n_views, const gs_camera* cams,
+                                        const gs_raster_cfg* cfg, int64_t capacity) {
+  return bin_sort_ws(n, n_views, cams, cfg, capacity);
+}
+
+gs_status gs_bin_sort_views(int64_t n, int32_t n_views, const gs_camera* cams,
+                            const gs_raster_cfg* cfg, const float* depth, const int32_t* rect,
+                            int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
+                            int64_t* n_pairs_dev, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  g_msg[0] = 0;
+  if (!n_pairs_dev) return fail(GS_ERR_INVALID_ARGUMENT, "gs_bin_sort_views: n_pairs_dev is NULL");
+  return bin_sort_impl("gs_bin_sort_views", n, n_views, cams, cfg, depth, rect, capacity,
+                       sorted_ids, tile_ranges, nullptr, n_pairs_dev, workspace, workspace_bytes,
+                       stream);
+}
+
+gs_status gs_raster_grad_views(const gs_splat* splats, const int32_t* sorted_ids,
+                               const int32_t* tile_ranges, int32_t n_views,
+                               const gs_camera* cams, const gs_raster_cfg* cfg,
+                               int32_t want_grads, float* out, int32_t* n_blend, void* stream) {
+  g_msg[0] = 0;
+  return raster_impl("gs_raster_grad_views", splats, sorted_ids, tile_ranges, n_views, cams, cfg,
+                     want_grads, out, n_blend, stream);
+}
+
+gs_status gs_upscale_hermite_views(const float* in, int32_t n_views, const int32_t* lo_sizes,
+                                   float* out, const int32_t* hi_sizes, int32_t band_rows,
+                                   void* stream) {
+  g_msg[0] = 0;
+  return upscale_impl("gs_upscale_hermite_views", in, n_views, lo_sizes, out, hi_sizes, band_rows,
+                      stream);
 }
 
 gs_status gs_fd_slopes(const float* img, int32_t w, int32_t h, float* out, void* stream) {

@@ -33,6 +33,14 @@ constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;  // elements per sort / scan block
 constexpr int kWaves = kThreads / 64;
 
+// Pair count a device-count pass works on: the emitted total when it fits the
+// capacity (and the int32 index range), else 0 so that every later pass and
+// the tile ranges see an empty pair list.
+__device__ __forceinline__ int64_t eff_count(const uint64_t* total, int64_t cap) {
+  const uint64_t k = *total;
+  return (k <= (uint64_t)cap && k < (uint64_t(1) << 31)) ? (int64_t)k : 0;
+}
+
 // ----------------------------------------------------------------------------
 // fill
 // ----------------------------------------------------------------------------
@@ -153,12 +161,18 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 
 template <int BITS>
 __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
-                                                                 int64_t m, int shift,
+                                                                 int64_t m, const uint64_t* m_dev,
+                                                                 int64_t cap, int shift,
                                                                  uint32_t* __restrict__ hist,
                                                                  int64_t nblocks) {
   constexpr int R = 1 << BITS;
   __shared__ uint32_t s_h[kWaves][R];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (m_dev) m = eff_count(m_dev, cap);
+  if ((int64_t)blockIdx.x * kTile >= m) {  // past the data: an empty column
+    for (int d = t; d < R; d += kThreads) hist[(int64_t)d * nblocks + blockIdx.x] = 0u;
+    return;
+  }
   for (int k = t; k < kWaves * R; k += kThreads) (&s_h[0][0])[k] = 0;
   const int64_t seg = (int64_t)blockIdx.x * kTile + wave * kSeg;
   uint32_t key[kRounds];
@@ -215,9 +229,12 @@ __global__ __launch_bounds__(kThreads) void hist_scan_kernel(uint32_t* __restric
 template <int BITS>
 __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in /* null: index */,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t m, int shift,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int64_t nblocks) {
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t m,
+    const uint64_t* m_dev, int64_t cap, int shift, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ totals, int64_t nblocks) {
   constexpr int R = 1 << BITS;
+  if (m_dev) m = eff_count(m_dev, cap);
+  if ((int64_t)blockIdx.x * kTile >= m) return;
   constexpr int DPT = R > kThreads ? R / kThreads : 1;  // digits per thread in the digit phases
   __shared__ uint32_t s_keys[kTile];
   __shared__ uint32_t s_vals[kTile];
@@ -329,32 +346,35 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   }
 }
 
+// A pass over m elements, or, with m_dev set, over the device-side count
+// eff_count(m_dev, m) with m (the capacity) sizing the grid.
 template <int BITS>
 hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
-                           uint32_t* vout, int64_t m, int shift, uint32_t* hist,
-                           uint32_t* totals, hipStream_t stream) {
-  const int64_t nb = ceil_div(m, kTile);
-  radix_upsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, m, shift, hist, nb);
+                           uint32_t* vout, int64_t m, const uint64_t* m_dev, int shift,
+                           uint32_t* hist, uint32_t* totals, hipStream_t stream) {
+  const int64_t nb = std::max<int64_t>(ceil_div(m, kTile), 1);
+  radix_upsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, m, m_dev, m, shift, hist,
+                                                                     nb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hist_scan_kernel<<<1u << BITS, kThreads, 0, stream>>>(hist, nb, totals);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  radix_downsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, vin, kout, vout, m,
-                                                                       shift, hist, totals, nb);
+  radix_downsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(
+      kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb);
   return hipGetLastError();
 }
 
 // One stable pass over `bits` (1..kMaxDigitBits) bits starting at `shift`.
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                      int64_t m, int shift, int bits, uint32_t* hist, uint32_t* totals,
-                      hipStream_t stream) {
+                      int64_t m, const uint64_t* m_dev, int shift, int bits, uint32_t* hist,
+                      uint32_t* totals, hipStream_t stream) {
   switch (bits) {
 #define GS_RADIX_CASE(B)                                                                  \
   case B:                                                                                 \
     if (B <= kMaxDigitBits)                                                               \
-      return radix_pass_bits<(B <= kMaxDigitBits ? B : 1)>(kin, vin, kout, vout, m, shift, \
-                                                           hist, totals, stream);         \
+      return radix_pass_bits<(B <= kMaxDigitBits ? B : 1)>(kin, vin, kout, vout, m, m_dev,  \
+                                                           shift, hist, totals, stream);  \
     break;
     GS_RADIX_CASE(1)
     GS_RADIX_CASE(2)
@@ -395,19 +415,26 @@ __device__ __forceinline__ uint32_t rect_tiles(int4 r) {
 
 constexpr int kEmit = 256;  // splats per gather / emit block
 
-// Rectangles in depth order (clipped) and, per block of kEmit splats, the sum
-// of their tile counts.
+// View of splat record e: splats of view v are e in [v n, (v + 1) n).
+__device__ __forceinline__ int view_of(const ViewTiles& vt, uint32_t e) {
+  return vt.nv > 1 ? (int)(e / (uint32_t)vt.n) : 0;
+}
+
+// Rectangles in depth order (clipped to their view's tile grid) and, per
+// block of kEmit splats, the sum of their tile counts.
 __global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
                                                             const uint32_t* __restrict__ order,
                                                             const int4* __restrict__ rect,
-                                                            int32_t tiles_x, int32_t tiles_y,
+                                                            ViewTiles vt,
                                                             int4* __restrict__ srect,
                                                             uint64_t* __restrict__ bsum) {
   __shared__ uint64_t s_w[kEmit / 64];
   const int64_t p = (int64_t)blockIdx.x * kEmit + threadIdx.x;
   uint64_t c = 0;
   if (p < n) {
-    const int4 r = clip_rect(rect[order[p]], tiles_x, tiles_y);
+    const uint32_t e = order[p];
+    const int v = view_of(vt, e);
+    const int4 r = clip_rect(rect[e], vt.tiles_x[v], vt.tiles_y[v]);
     srect[p] = r;
     c = rect_tiles(r);
   }
@@ -420,13 +447,16 @@ __global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
 // order), whose pairs form one contiguous range starting at boff[block]; the
 // block scans its splats' tile counts in LDS, then every thread writes one
 // pair per step, finding its splat by binary search over those offsets, so
-// the writes are coalesced whatever the splats' tile counts.  Only runs once
-// the total is known to be below 2^31.
+// the writes are coalesced whatever the splats' tile counts.  Tile keys are
+// global: view v's tiles are numbered from tile_off[v].  With `total` set
+// (device-side count) nothing is written unless the total fits `cap`.
 __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* __restrict__ order,
                                                      const int4* __restrict__ srect,
                                                      const uint64_t* __restrict__ boff,
-                                                     int32_t tiles_x, uint32_t* __restrict__ tkeys,
+                                                     ViewTiles vt, const uint64_t* total,
+                                                     int64_t cap, uint32_t* __restrict__ tkeys,
                                                      uint32_t* __restrict__ tvals) {
+  if (total && eff_count(total, cap) == 0) return;
   __shared__ uint32_t s_off[kEmit + 1];
   __shared__ int4 s_rect[kEmit];
   __shared__ uint32_t s_gid[kEmit];
@@ -456,6 +486,8 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
       else hi = mid;
     }
     const int4 r = s_rect[lo];
+    const uint32_t gid = s_gid[lo];
+    const int v = view_of(vt, gid);
     const uint32_t li = k - s_off[lo];
     const uint32_t w = (uint32_t)(r.z - r.x);
     // row / column inside the rectangle; the float quotient is exact to +-1
@@ -468,18 +500,21 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
       ++dy;
       dx -= (int)w;
     }
-    tkeys[base + k] = (uint32_t)(r.y + dy) * (uint32_t)tiles_x + (uint32_t)(r.x + dx);
-    tvals[base + k] = s_gid[lo];
+    tkeys[base + k] =
+        vt.tile_off[v] + (uint32_t)(r.y + dy) * (uint32_t)vt.tiles_x[v] + (uint32_t)(r.x + dx);
+    tvals[base + k] = gid;
   }
 }
 
 // Tile ranges from the tile-sorted keys: a block stages kTile keys plus one
 // neighbour on each side in LDS and marks where the tile id changes.
-__global__ __launch_bounds__(kThreads) void tile_range_kernel(int64_t K,
+__global__ __launch_bounds__(kThreads) void tile_range_kernel(int64_t K, const uint64_t* K_dev,
                                                               const uint32_t* __restrict__ tkeys,
                                                               int32_t* __restrict__ ranges) {
   __shared__ uint32_t s_k[kTile + 2];
+  if (K_dev) K = eff_count(K_dev, K);
   const int64_t base = (int64_t)blockIdx.x * kTile;
+  if (base >= K) return;
   for (int i = threadIdx.x; i < kTile + 2; i += kThreads) {
     const int64_t p = base + i - 1;
     s_k[i] = (p >= 0 && p < K) ? tkeys[p] : 0xFFFFFFFFu;
@@ -498,14 +533,26 @@ inline unsigned grid1d(int64_t n, int threads) { return (unsigned)ceil_div(n, th
 
 }  // namespace
 
-BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int32_t width, int32_t height,
-                               int32_t tile_size) {
+ViewTiles make_view_tiles(int32_t nv, const gs_camera* cams, int32_t tile_size, int64_t n) {
+  ViewTiles vt{};
+  vt.nv = nv;
+  vt.n = n;
+  uint32_t off = 0;
+  for (int v = 0; v < nv; ++v) {
+    vt.tiles_x[v] = (int32_t)ceil_div(cams[v].width, tile_size);
+    vt.tiles_y[v] = (int32_t)ceil_div(cams[v].height, tile_size);
+    vt.tile_off[v] = off;
+    off += (uint32_t)vt.tiles_x[v] * (uint32_t)vt.tiles_y[v];
+  }
+  vt.tile_off[nv] = off;
+  return vt;
+}
+
+BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles) {
   BinSortPlan p;
   p.n = n;
   p.capacity = capacity;
-  p.tiles_x = ceil_div(width, tile_size);
-  p.tiles_y = ceil_div(height, tile_size);
-  p.tiles = p.tiles_x * p.tiles_y;
+  p.tiles = tiles;
   int bits = 1;
   while ((int64_t(1) << bits) < p.tiles) ++bits;
   p.tile_bits = bits;
@@ -537,15 +584,19 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int32_t width, int32
   return p;
 }
 
-gs_status run_bin_sort(const BinSortPlan& p, const float* depth, const int32_t* rect,
-                       int32_t* sorted_ids, int32_t* tile_ranges, int64_t* n_pairs,
-                       void* workspace, hipStream_t stream) {
+gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* depth,
+                       const int32_t* rect, int32_t* sorted_ids, int32_t* tile_ranges,
+                       int64_t* n_pairs, int64_t* n_pairs_dev, void* workspace,
+                       hipStream_t stream) {
   char* ws = static_cast<char*>(workspace);
   auto u32 = [&](size_t o) { return reinterpret_cast<uint32_t*>(ws + o); };
   uint64_t* bsum = reinterpret_cast<uint64_t*>(ws + p.off_bsum);
   uint32_t* hist = u32(p.off_hist);
   uint32_t* totals = u32(p.off_totals);
-  uint64_t* total = reinterpret_cast<uint64_t*>(ws + p.off_total);
+  // device-count mode: the total goes straight to the caller's counter
+  const bool dev = n_pairs_dev != nullptr;
+  uint64_t* total = dev ? reinterpret_cast<uint64_t*>(n_pairs_dev)
+                        : reinterpret_cast<uint64_t*>(ws + p.off_total);
   const int4* r4 = reinterpret_cast<const int4*>(rect);
   const int64_t n = p.n;
   hipError_t e;
@@ -556,22 +607,24 @@ gs_status run_bin_sort(const BinSortPlan& p, const float* depth, const int32_t* 
   } while (0)
 
   if (n == 0) {
-    *n_pairs = 0;
+    if (n_pairs) *n_pairs = 0;
+    if (dev) fill_i32_kernel<<<1, 64, 0, stream>>>(reinterpret_cast<int32_t*>(total), 2, 0);
     fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
     return check_hip(hipGetLastError(), "fill_i32_kernel");
   }
   // 1. depth order of all splats: stable LSD radix sort of the FP32 depth bits
   //    (positive floats order like their bits; +inf marks splats without
-  //    tiles); the first pass reads the depths in place and numbers them
-  const int32_t tx = (int32_t)p.tiles_x, ty = (int32_t)p.tiles_y;
+  //    tiles); the first pass reads the depths in place and numbers them.
+  //    Several views sort together: a tile only ever holds splats of one
+  //    view, so the global order restricted to a tile is that view's order.
   int widths[8];
   int passes = radix_plan(32, widths);
   int cur = 0, shift = 0;
   for (int k = 0; k < passes; ++k) {
     const uint32_t* kin = k == 0 ? reinterpret_cast<const uint32_t*>(depth) : u32(p.off_gkey[cur]);
     const uint32_t* vin = k == 0 ? nullptr : u32(p.off_gval[cur]);
-    GS_TRY(radix_pass(kin, vin, u32(p.off_gkey[cur ^ 1]), u32(p.off_gval[cur ^ 1]), n, shift,
-                      widths[k], hist, totals, stream),
+    GS_TRY(radix_pass(kin, vin, u32(p.off_gkey[cur ^ 1]), u32(p.off_gval[cur ^ 1]), n, nullptr,
+                      shift, widths[k], hist, totals, stream),
            "depth radix pass");
     shift += widths[k];
     cur ^= 1;
@@ -581,46 +634,52 @@ gs_status run_bin_sort(const BinSortPlan& p, const float* depth, const int32_t* 
   // 2. rectangles in depth order, pair offsets per block of splats, total K
   int4* srect = reinterpret_cast<int4*>(ws + p.off_srect);
   const int64_t nbe = ceil_div(n, kEmit);
-  gather_rect_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, r4, tx, ty, srect, bsum);
+  gather_rect_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, r4, vt, srect, bsum);
   GS_TRY(hipGetLastError(), "gather_rect_kernel");
   scan_small_kernel<uint64_t><<<1, kSmallThreads, 0, stream>>>(bsum, nbe, total);
   GS_TRY(hipGetLastError(), "pair offset scan");
-  uint64_t K = 0;
-  GS_TRY(hipMemcpyAsync(&K, total, sizeof(K), hipMemcpyDeviceToHost, stream), "pair count copy");
-  GS_TRY(hipStreamSynchronize(stream), "pair count sync");
-  *n_pairs = (int64_t)K;
-  if (K >= (uint64_t(1) << 31))
-    return fail(GS_ERR_CAPACITY, "gs_bin_sort: %llu pairs exceed the 2^31 index limit",
-                (unsigned long long)K);
-  if ((int64_t)K > p.capacity)
-    return fail(GS_ERR_CAPACITY, "gs_bin_sort: %llu pairs exceed capacity %lld",
-                (unsigned long long)K, (long long)p.capacity);
+  int64_t m = p.capacity;  // device-count mode: grids sized by the capacity
+  if (!dev) {
+    uint64_t K = 0;
+    GS_TRY(hipMemcpyAsync(&K, total, sizeof(K), hipMemcpyDeviceToHost, stream), "pair count copy");
+    GS_TRY(hipStreamSynchronize(stream), "pair count sync");
+    *n_pairs = (int64_t)K;
+    if (K >= (uint64_t(1) << 31))
+      return fail(GS_ERR_CAPACITY, "gs_bin_sort: %llu pairs exceed the 2^31 index limit",
+                  (unsigned long long)K);
+    if ((int64_t)K > p.capacity)
+      return fail(GS_ERR_CAPACITY, "gs_bin_sort: %llu pairs exceed capacity %lld",
+                  (unsigned long long)K, (long long)p.capacity);
+    m = (int64_t)K;
+  }
+  const uint64_t* m_dev = dev ? total : nullptr;
 
   // 3. empty ranges, then pairs in depth order
   fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
   GS_TRY(hipGetLastError(), "fill_i32_kernel");
-  if (K == 0) return GS_OK;
+  if (m == 0) return GS_OK;
   passes = radix_plan(p.tile_bits, widths);
   // values end in sorted_ids after `passes` ping-pong steps
   uint32_t* vbuf[2];
   vbuf[0] = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(sorted_ids) : u32(p.off_pval);
   vbuf[1] = (passes % 2 == 0) ? u32(p.off_pval) : reinterpret_cast<uint32_t*>(sorted_ids);
   uint32_t* kbuf[2] = {u32(p.off_pkey[0]), u32(p.off_pkey[1])};
-  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, srect, bsum, tx, kbuf[0], vbuf[0]);
+  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, srect, bsum, vt, m_dev, p.capacity,
+                                                   kbuf[0], vbuf[0]);
   GS_TRY(hipGetLastError(), "emit_kernel");
 
   // 4. stable sort of the pairs by tile id
   cur = 0;
   shift = 0;
   for (int k = 0; k < passes; ++k) {
-    GS_TRY(radix_pass(kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], (int64_t)K, shift,
+    GS_TRY(radix_pass(kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], m, m_dev, shift,
                       widths[k], hist, totals, stream),
            "tile radix pass");
     shift += widths[k];
     cur ^= 1;
   }
-  tile_range_kernel<<<(unsigned)ceil_div((int64_t)K, kTile), kThreads, 0, stream>>>(
-      (int64_t)K, kbuf[cur], tile_ranges);
+  tile_range_kernel<<<(unsigned)ceil_div(m, kTile), kThreads, 0, stream>>>(m, m_dev, kbuf[cur],
+                                                                           tile_ranges);
   GS_TRY(hipGetLastError(), "tile_range_kernel");
 #undef GS_TRY
   return GS_OK;

@@ -31,16 +31,27 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t grid) {
 }
 
 // ---- projection (project.hip) ------------------------------------------------
+// Views v of a batch write splats / depth / rect at offset v * n.
 hipError_t launch_project(int64_t n, const float* means, const float* log_scales,
-                          const float* quats, const float* opacity, const float* sh,
-                          const gs_camera& cam, const gs_raster_cfg& cfg, gs_splat* splats,
+                          const float* quats, const float* opacity, const float* sh, int32_t nv,
+                          const gs_camera* cams, const gs_raster_cfg& cfg, gs_splat* splats,
                           float* depth, int32_t* rect, hipStream_t stream);
 
 // ---- binning and sorting (binsort.hip) --------------------------------------
+// Tile grids of the views of a batch; view v's tiles have the global ids
+// tile_off[v] .. tile_off[v+1) (row-major inside the view).
+struct ViewTiles {
+  int32_t nv = 1;
+  int64_t n = 0;  // splats per view
+  int32_t tiles_x[GS_MAX_VIEWS], tiles_y[GS_MAX_VIEWS];
+  uint32_t tile_off[GS_MAX_VIEWS + 1];
+};
+ViewTiles make_view_tiles(int32_t nv, const gs_camera* cams, int32_t tile_size, int64_t n);
+
 struct BinSortPlan {
-  int64_t n = 0;          // splats
+  int64_t n = 0;          // splat records (all views)
   int64_t capacity = 0;   // pair capacity
-  int64_t tiles_x = 0, tiles_y = 0, tiles = 0;
+  int64_t tiles = 0;      // tiles of all views
   int tile_bits = 0;      // bits of the tile id key
   // workspace layout (byte offsets)
   size_t off_gkey[2], off_gval[2];  // depth keys / splat ids, ping-pong [n]
@@ -48,26 +59,32 @@ struct BinSortPlan {
   size_t off_srect;                 // clipped tile rectangles in depth order [n]
   size_t off_pkey[2];               // pair tile keys, ping-pong [capacity]
   size_t off_pval;                  // pair ids, second buffer [capacity]
-  size_t off_hist;                  // radix digit counts [2^11 * max blocks]
-  size_t off_totals;                // per-digit totals [2^11]
+  size_t off_hist;                  // radix digit counts [2^digit bits * max blocks]
+  size_t off_totals;                // per-digit totals
   size_t off_total;                 // 1 x uint64 pair total
   size_t bytes = 0;
 };
-BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int32_t width, int32_t height,
-                               int32_t tile_size);
-gs_status run_bin_sort(const BinSortPlan& plan, const float* depth, const int32_t* rect,
-                       int32_t* sorted_ids, int32_t* tile_ranges, int64_t* n_pairs,
-                       void* workspace, hipStream_t stream);
+BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles);
+// Host-count mode (n_pairs_dev == NULL): reads K to *n_pairs, waits once and
+// fails with GS_ERR_CAPACITY when it does not fit.  Device-count mode: never
+// waits; K goes to *n_pairs_dev and an oversized K leaves every range empty.
+gs_status run_bin_sort(const BinSortPlan& plan, const ViewTiles& vt, const float* depth,
+                       const int32_t* rect, int32_t* sorted_ids, int32_t* tile_ranges,
+                       int64_t* n_pairs, int64_t* n_pairs_dev, void* workspace,
+                       hipStream_t stream);
 
 // ---- rasterization (raster.hip) -----------------------------------------------
+// One launch over the tiles of all views; view v's pixels go to
+// out + (sum of earlier views' pixels) * channels, likewise n_blend.
 hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
-                         const int32_t* tile_ranges, const gs_camera& cam,
+                         const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,
                          const gs_raster_cfg& cfg, bool grads, float* out, int32_t* n_blend,
                          hipStream_t stream);
 
 // ---- upscaling (upscale.hip) ---------------------------------------------------
-hipError_t launch_upscale(const float* in, int32_t w, int32_t h, float* out, int32_t W,
-                          int32_t H, hipStream_t stream);
+// Views are concatenated in both buffers; sizes are host arrays [nv][2].
+hipError_t launch_upscale(const float* in, int32_t nv, const int32_t* lo_sizes, float* out,
+                          const int32_t* hi_sizes, int32_t band_rows, hipStream_t stream);
 hipError_t launch_fd_slopes(const float* img, int32_t w, int32_t h, float* out,
                             hipStream_t stream);
 

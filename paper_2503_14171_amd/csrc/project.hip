@@ -27,17 +27,22 @@ constexpr double kRectMargin = 0.25;
 // multiple of the half field of view (keeps off-screen footprints finite).
 constexpr double kFrustumClamp = 1.3;
 
-struct ProjParams {
-  int64_t n;
-  int32_t width, height, tile;
-  int32_t sh_degree;
+// Camera of one view of a batch.
+struct ProjView {
+  int32_t width, height;
   double fx, fy, cx, cy;
   double V[12];
   double cam[3];
   double near_plane;
+  double limx, limy;
+};
+
+struct ProjParams {
+  int64_t n;  // Gaussians (per view)
+  int32_t nv, tile;
   double dilation;
   double alpha_min, log_alpha_min;
-  double limx, limy;
+  ProjView view[GS_MAX_VIEWS];
 };
 
 // Real orthonormal SH basis (graphics sign convention, Condon-Shortley phase
@@ -83,8 +88,19 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
                                                       gs_splat* __restrict__ splats,
                                                       float* __restrict__ depth_out,
                                                       int4* __restrict__ rect_out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // Several views: the views of one chunk of Gaussians are adjacent logical
+  // blocks of one XCD, so the chunk's parameters are fetched into its L2 once.
+  int vi = 0;
+  int64_t chunk = blockIdx.x;
+  if (p.nv > 1) {
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    vi = (int)(lb % p.nv);
+    chunk = lb / p.nv;
+  }
+  const int64_t i = chunk * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
+  const ProjView& cv = p.view[vi];
+  const int64_t o = (int64_t)vi * p.n + i;  // output record
   constexpr int nb = (DEG + 1) * (DEG + 1);
 
   const double mu0 = means[3 * i], mu1 = means[3 * i + 1], mu2 = means[3 * i + 2];
@@ -96,7 +112,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
             isfinite(ls1) && isfinite(ls2) && isfinite(q4.x) && isfinite(q4.y) &&
             isfinite(q4.z) && isfinite(q4.w);
 
-  const double* V = p.V;
+  const double* V = cv.V;
   // camera-space position, summed left to right (products of FP32 values are
   // exact in FP64, so the depth is the correctly ordered sum)
   const double t0 = ((V[0] * mu0 + V[1] * mu1) + V[2] * mu2) + V[3];
@@ -104,7 +120,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
   const double t2 = ((V[8] * mu0 + V[9] * mu1) + V[10] * mu2) + V[11];
   const double qn2 = (double)q4.x * q4.x + (double)q4.y * q4.y + (double)q4.z * q4.z +
                      (double)q4.w * q4.w;
-  ok = ok && (t2 > p.near_plane) && (qn2 > 0.0) && ((double)sig >= p.alpha_min);
+  ok = ok && (t2 > cv.near_plane) && (qn2 > 0.0) && ((double)sig >= p.alpha_min);
 
   float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0;
   double2 m2 = make_double2(0.0, 0.0);
@@ -121,10 +137,10 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
     const double s2[3] = {exp(2.0 * ls0), exp(2.0 * ls1), exp(2.0 * ls2)};
     // M = J W (2x3); Sigma' = M R S^2 R^T M^T = (M R) S^2 (M R)^T
     const double tz = t2, itz = 1.0 / t2;
-    const double ux = fmin(p.limx, fmax(-p.limx, t0 * itz)) * tz;
-    const double uy = fmin(p.limy, fmax(-p.limy, t1 * itz)) * tz;
-    const double j00 = p.fx * itz, j02 = -p.fx * ux * itz * itz;
-    const double j11 = p.fy * itz, j12 = -p.fy * uy * itz * itz;
+    const double ux = fmin(cv.limx, fmax(-cv.limx, t0 * itz)) * tz;
+    const double uy = fmin(cv.limy, fmax(-cv.limy, t1 * itz)) * tz;
+    const double j00 = cv.fx * itz, j02 = -cv.fx * ux * itz * itz;
+    const double j11 = cv.fy * itz, j12 = -cv.fy * uy * itz * itz;
     double M[2][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -145,16 +161,16 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
     }
     const double det = sxx * syy - sxy * sxy;
     if (det > 0.0) {
-      const double mx = p.fx * t0 * itz + p.cx;
-      const double my = p.fy * t1 * itz + p.cy;
+      const double mx = cv.fx * t0 * itz + cv.cx;
+      const double my = cv.fy * t1 * itz + cv.cy;
       const double L = log((double)sig) - p.log_alpha_min;
       const double rx = sqrt(2.0 * L * sxx), ry = sqrt(2.0 * L * syy);
       double x0 = ceil(mx - rx - kRectMargin), x1 = floor(mx + rx + kRectMargin);
       double y0 = ceil(my - ry - kRectMargin), y1 = floor(my + ry + kRectMargin);
       x0 = fmax(x0, 0.0);
       y0 = fmax(y0, 0.0);
-      x1 = fmin(x1, (double)(p.width - 1));
-      y1 = fmin(y1, (double)(p.height - 1));
+      x1 = fmin(x1, (double)(cv.width - 1));
+      y1 = fmin(y1, (double)(cv.height - 1));
       if (x0 <= x1 && y0 <= y1) {
         // On screen: only now read the SH coefficients (3 nb floats), so the
         // splats that reach no tile cost no colour traffic.
@@ -179,7 +195,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
         for (int k = 0; k < 3 * nb; ++k) fin = fin && isfinite(coef[k]);
         if (fin) {
           // view-dependent colour
-          double dx = mu0 - p.cam[0], dy = mu1 - p.cam[1], dz = mu2 - p.cam[2];
+          double dx = mu0 - cv.cam[0], dy = mu1 - cv.cam[1], dz = mu2 - cv.cam[2];
           const double dn2 = dx * dx + dy * dy + dz * dz;
           if (dn2 > 0.0) {
             const double idn = 1.0 / sqrt(dn2);
@@ -212,41 +228,46 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
       }
     }
   }
-  double2* sp = reinterpret_cast<double2*>(splats + i);
+  double2* sp = reinterpret_cast<double2*>(splats + o);
   sp[0] = m2;
-  float4* sf = reinterpret_cast<float4*>(splats + i);
+  float4* sf = reinterpret_cast<float4*>(splats + o);
   sf[1] = w0;
   sf[2] = w1;
-  depth_out[i] = dep;
-  rect_out[i] = rect;
+  depth_out[o] = dep;
+  rect_out[o] = rect;
 }
 
 }  // namespace
 
 hipError_t launch_project(int64_t n, const float* means, const float* log_scales,
-                          const float* quats, const float* opacity, const float* sh,
-                          const gs_camera& cam, const gs_raster_cfg& cfg, gs_splat* splats,
+                          const float* quats, const float* opacity, const float* sh, int32_t nv,
+                          const gs_camera* cams, const gs_raster_cfg& cfg, gs_splat* splats,
                           float* depth, int32_t* rect, hipStream_t stream) {
-  ProjParams p;
+  ProjParams p{};
   p.n = n;
-  p.width = cam.width;
-  p.height = cam.height;
+  p.nv = nv;
   p.tile = cfg.tile_size;
-  p.sh_degree = cfg.sh_degree;
-  p.fx = cam.fx;
-  p.fy = cam.fy;
-  p.cx = cam.cx;
-  p.cy = cam.cy;
-  for (int k = 0; k < 12; ++k) p.V[k] = cam.view[k];
-  for (int k = 0; k < 3; ++k) p.cam[k] = cam.cam_pos[k];
-  p.near_plane = cam.near_plane;
   p.dilation = cfg.dilation;
   p.alpha_min = cfg.alpha_min;
   p.log_alpha_min = log((double)cfg.alpha_min);
-  p.limx = kFrustumClamp * (0.5 * cam.width) / (double)cam.fx;
-  p.limy = kFrustumClamp * (0.5 * cam.height) / (double)cam.fy;
+  for (int v = 0; v < nv; ++v) {
+    const gs_camera& cam = cams[v];
+    ProjView& c = p.view[v];
+    c.width = cam.width;
+    c.height = cam.height;
+    c.fx = cam.fx;
+    c.fy = cam.fy;
+    c.cx = cam.cx;
+    c.cy = cam.cy;
+    for (int k = 0; k < 12; ++k) c.V[k] = cam.view[k];
+    for (int k = 0; k < 3; ++k) c.cam[k] = cam.cam_pos[k];
+    c.near_plane = cam.near_plane;
+    c.limx = kFrustumClamp * (0.5 * cam.width) / (double)cam.fx;
+    c.limy = kFrustumClamp * (0.5 * cam.height) / (double)cam.fy;
+  }
   const int threads = 256;
-  const int64_t blocks = ceil_div(n, threads);
+  const int64_t chunks = ceil_div(n, threads);
+  const int64_t blocks = nv > 1 ? xcd_grid(chunks * nv) : chunks;
   int4* r4 = reinterpret_cast<int4*>(rect);
   const dim3 g((unsigned)blocks), b(threads);
   switch (cfg.sh_degree) {

@@ -18,8 +18,8 @@
 //
 // Work decomposition (gfx950): one workgroup per screen tile (8x8, 16x16 or
 // 32x32 pixels), one pixel per lane, and every wave64 owns one 8x8 quadrant
-// of the tile.  The tile's splats stream through LDS in batches of one splat
-// per thread; while staging, each thread marks the quadrants its splat's
+// of the tile.  The tile's splats stream through LDS in batches of up to one
+// splat per thread (BATCH = TILE^2, or TILE^2/2, TILE^2/4); while staging, each thread marks the quadrants its splat's
 // support box meets, and each wave then compacts the batch (ballot + prefix
 // popcount) into its own LDS list of hits in depth order, so a wave only
 // evaluates splats that can reach its 64 pixels.  Every lane reads the same
@@ -29,24 +29,35 @@
 // batches once a barrier count shows no live pixel.  Splat means are held in
 // FP64 and turned into tile-relative FP32 offsets when staged into LDS, so
 // pixel - mean is exact at any image coordinate.  Blocks are renumbered so
-// that each XCD (own L2) works on a contiguous band of tiles.
+// that each XCD (own L2) works on a contiguous band of tiles.  Several views
+// go through one launch: the grid covers the tiles of all views, numbered
+// view after view, and each workgroup finds its view from the tile id.
 #include "gsup_internal.h"
 
 namespace gsup {
 namespace {
 
-struct RasterParams {
+// One view of a batch: its raster, its first global tile id and the offset
+// of its first pixel in the concatenated outputs.
+struct RasterView {
   int32_t width, height, tiles_x;
-  int64_t tiles;
+  uint32_t tile_off;
+  int64_t pix_off;
+};
+
+struct RasterParams {
+  int32_t nv;
+  int64_t tiles;  // all views
   float alpha_max, t_min;
   float bg[3];
+  RasterView view[GS_MAX_VIEWS];
 };
 
 // Widening, in pixels, of a splat's support box in the per-wave culling test
 // (covers FP32 rounding of the box and of the per-pixel alpha test).
 constexpr float kCullMargin = 0.25f;
 
-template <int TILE, bool GRAD>
+template <int TILE, bool GRAD, int BATCH>
 __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
                                                             const gs_splat* __restrict__ splats,
                                                             const int32_t* __restrict__ ids,
@@ -57,19 +68,24 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
   constexpr int NW = NT / 64;   // waves; wave w owns one 8x8 quadrant of the tile
   constexpr int QX = TILE / 8;  // quadrants per tile row
   constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
-  __shared__ float4 s_a[NT];  // mean x, mean y (tile-relative), conic a, conic b
-  __shared__ float4 s_b[NT];  // conic c, log2 sigma, support, red
-  __shared__ float2 s_c[NT];  // green, blue
-  __shared__ uint32_t s_mask[NW > 1 ? NT : 1];             // quadrants a staged splat can reach
-  __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? NT : 1];  // per-wave hits, batch order
+  static_assert(BATCH >= 16 && BATCH <= NT, "one splat per staging thread");
+  __shared__ float4 s_a[BATCH];  // mean x, mean y (tile-relative), conic a, conic b
+  __shared__ float4 s_b[BATCH];  // conic c, log2 sigma, support, red
+  __shared__ float2 s_c[BATCH];  // green, blue
+  __shared__ uint32_t s_mask[NW > 1 ? BATCH : 1];                // quadrants a staged splat can reach
+  __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];  // per-wave hits, batch order
 
   const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
   if (tile >= p.tiles) return;
+  int vi = 0;  // the view this tile belongs to (uniform over the block)
+  while (vi + 1 < p.nv && (uint32_t)tile >= p.view[vi + 1].tile_off) ++vi;
+  const int width = p.view[vi].width, height = p.view[vi].height, tiles_x = p.view[vi].tiles_x;
+  const int64_t local = tile - p.view[vi].tile_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int tx = (int)(tile % p.tiles_x), ty = (int)(tile / p.tiles_x);
+  const int tx = (int)(local % tiles_x), ty = (int)(local / tiles_x);
   const int lx = (wave % QX) * 8 + (lane & 7), ly = (wave / QX) * 8 + (lane >> 3);
   const int px = tx * TILE + lx, py = ty * TILE + ly;
-  const bool inside = px < p.width && py < p.height;
+  const bool inside = px < width && py < height;
   const float fx = (float)lx, fy = (float)ly;
   const double ox = (double)tx * TILE, oy = (double)ty * TILE;
   const int2 rg = ranges[tile];
@@ -82,12 +98,12 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
   float Bxy0 = 0.f, Bxy1 = 0.f, Bxy2 = 0.f;
   int nb = 0;
 
-  for (int base = rg.x; base < rg.y; base += NT) {
+  for (int base = rg.x; base < rg.y; base += BATCH) {
     if (__syncthreads_count(!done) == 0) break;
-    // stage one splat per thread
+    // stage one splat per thread of the first BATCH threads
     const int idx = base + t;
     uint32_t mask = 0;
-    if (idx < rg.y) {
+    if (t < BATCH && idx < rg.y) {
       const float4* s = reinterpret_cast<const float4*>(splats + ids[idx]);
       const double2 m = *reinterpret_cast<const double2*>(s);
       const float4 q = s[1];  // a, b, c, sigma
@@ -115,9 +131,9 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
         }
       }
     }
-    if (NW > 1) s_mask[t] = mask;
+    if (NW > 1 && t < BATCH) s_mask[t] = mask;
     __syncthreads();
-    const int cnt = min(NT, rg.y - base);
+    const int cnt = min(BATCH, rg.y - base);
     int nl = cnt;
     if (NW > 1) {
       // this wave's splats of the batch, in batch (= depth) order
@@ -183,7 +199,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
     }
   }
   if (!inside) return;
-  const int64_t pix = (int64_t)py * p.width + px;
+  const int64_t pix = p.view[vi].pix_off + (int64_t)py * width + px;
   if (GRAD) {
     float4* o = reinterpret_cast<float4*>(out + pix * 12);
     o[0] = make_float4(fmaf(T, p.bg[0], B0), fmaf(T, p.bg[1], B1), fmaf(T, p.bg[2], B2),
@@ -201,38 +217,57 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
   if (n_blend) n_blend[pix] = nb;
 }
 
-template <int TILE, bool GRAD>
+template <int TILE, bool GRAD, int BATCH>
 void launch(const RasterParams& p, const gs_splat* splats, const int32_t* ids, const int2* ranges,
             float* out, int32_t* n_blend, hipStream_t stream) {
   const int64_t grid = xcd_grid(p.tiles);
-  raster_kernel<TILE, GRAD><<<(unsigned)grid, TILE * TILE, 0, stream>>>(p, splats, ids, ranges,
-                                                                       out, n_blend);
+  raster_kernel<TILE, GRAD, BATCH><<<(unsigned)grid, TILE * TILE, 0, stream>>>(
+      p, splats, ids, ranges, out, n_blend);
+}
+
+// batch: 0 or TILE^2 -> one splat per thread; TILE^2 / 2 and TILE^2 / 4 -> fewer
+template <int TILE, bool GRAD>
+void launch_batch(int batch, const RasterParams& p, const gs_splat* splats, const int32_t* ids,
+                  const int2* ranges, float* out, int32_t* n_blend, hipStream_t stream) {
+  constexpr int NT = TILE * TILE;
+  if (batch == NT / 4) launch<TILE, GRAD, NT / 4>(p, splats, ids, ranges, out, n_blend, stream);
+  else if (batch == NT / 2) launch<TILE, GRAD, NT / 2>(p, splats, ids, ranges, out, n_blend, stream);
+  else launch<TILE, GRAD, NT>(p, splats, ids, ranges, out, n_blend, stream);
 }
 
 }  // namespace
 
 hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
-                         const int32_t* tile_ranges, const gs_camera& cam,
+                         const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,
                          const gs_raster_cfg& cfg, bool grads, float* out, int32_t* n_blend,
                          hipStream_t stream) {
-  RasterParams p;
-  p.width = cam.width;
-  p.height = cam.height;
-  p.tiles_x = (int32_t)ceil_div(cam.width, cfg.tile_size);
-  p.tiles = (int64_t)p.tiles_x * ceil_div(cam.height, cfg.tile_size);
+  RasterParams p{};
+  p.nv = nv;
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < nv; ++v) {
+    RasterView& rv = p.view[v];
+    rv.width = cams[v].width;
+    rv.height = cams[v].height;
+    rv.tiles_x = (int32_t)ceil_div(cams[v].width, cfg.tile_size);
+    rv.tile_off = (uint32_t)tiles;
+    rv.pix_off = pix;
+    tiles += (int64_t)rv.tiles_x * ceil_div(cams[v].height, cfg.tile_size);
+    pix += (int64_t)cams[v].width * cams[v].height;
+  }
+  p.tiles = tiles;
   p.alpha_max = cfg.alpha_max;
   p.t_min = cfg.t_min;
   for (int k = 0; k < 3; ++k) p.bg[k] = cfg.bg[k];
   const int2* r2 = reinterpret_cast<const int2*>(tile_ranges);
   if (cfg.tile_size == 8) {
-    if (grads) launch<8, true>(p, splats, sorted_ids, r2, out, n_blend, stream);
-    else launch<8, false>(p, splats, sorted_ids, r2, out, n_blend, stream);
+    if (grads) launch_batch<8, true>(cfg.batch, p, splats, sorted_ids, r2, out, n_blend, stream);
+    else launch_batch<8, false>(cfg.batch, p, splats, sorted_ids, r2, out, n_blend, stream);
   } else if (cfg.tile_size == 16) {
-    if (grads) launch<16, true>(p, splats, sorted_ids, r2, out, n_blend, stream);
-    else launch<16, false>(p, splats, sorted_ids, r2, out, n_blend, stream);
+    if (grads) launch_batch<16, true>(cfg.batch, p, splats, sorted_ids, r2, out, n_blend, stream);
+    else launch_batch<16, false>(cfg.batch, p, splats, sorted_ids, r2, out, n_blend, stream);
   } else {
-    if (grads) launch<32, true>(p, splats, sorted_ids, r2, out, n_blend, stream);
-    else launch<32, false>(p, splats, sorted_ids, r2, out, n_blend, stream);
+    if (grads) launch_batch<32, true>(cfg.batch, p, splats, sorted_ids, r2, out, n_blend, stream);
+    else launch_batch<32, false>(cfg.batch, p, splats, sorted_ids, r2, out, n_blend, stream);
   }
   return hipGetLastError();
 }

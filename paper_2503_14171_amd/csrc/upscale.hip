@@ -68,14 +68,35 @@ __device__ __forceinline__ void row_terms(const float* __restrict__ in, int w, i
   D[2] = fmaf(h0, a2.x, fmaf(h1, b2.x, fmaf(h2, a2.w, h3 * b2.w)));
 }
 
+// One view of a batch: sizes, offsets (in pixels) into the concatenated
+// buffers, and its first logical block.
+struct UpView {
+  int32_t w, h, W, H, strips;
+  int64_t in_off, out_off, blk_off;
+};
+
+struct UpParams {
+  int32_t nv;
+  int64_t blocks;  // logical blocks of all views
+  UpView view[GS_MAX_VIEWS];
+};
+
 template <int ROWS>
-__global__ __launch_bounds__(kThreads) void upscale_kernel(const float* __restrict__ in, int w,
-                                                           int h, float* __restrict__ out, int W,
-                                                           int H, int strips) {
+__global__ __launch_bounds__(kThreads) void upscale_kernel(UpParams p,
+                                                           const float* __restrict__ in_all,
+                                                           float* __restrict__ out_all) {
   // bands of one XCD are contiguous, so the low-res row two bands share is
   // fetched into one L2
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int bx = (int)(blk % strips), by = (int)(blk / strips);
+  if (blk >= p.blocks) return;
+  int vi = 0;  // uniform over the block
+  while (vi + 1 < p.nv && blk >= p.view[vi + 1].blk_off) ++vi;
+  const int w = p.view[vi].w, h = p.view[vi].h, W = p.view[vi].W, H = p.view[vi].H;
+  const int strips = p.view[vi].strips;
+  const int64_t local = blk - p.view[vi].blk_off;
+  const float* __restrict__ in = in_all + p.view[vi].in_off * 12;
+  float* __restrict__ out = out_all + p.view[vi].out_off * 3;
+  const int bx = (int)(local % strips), by = (int)(local / strips);
   const int X = bx * kThreads + threadIdx.x;
   const int Y0 = by * ROWS;
   if (X >= W || Y0 >= H) return;
@@ -118,12 +139,35 @@ __global__ __launch_bounds__(kThreads) void upscale_kernel(const float* __restri
 
 }  // namespace
 
-hipError_t launch_upscale(const float* in, int32_t w, int32_t h, float* out, int32_t W, int32_t H,
-                          hipStream_t stream) {
-  constexpr int kRows = 16;
-  const int strips = (int)ceil_div(W, kThreads);
-  const int64_t blocks = xcd_grid((int64_t)strips * ceil_div(H, kRows));
-  upscale_kernel<kRows><<<(unsigned)blocks, kThreads, 0, stream>>>(in, w, h, out, W, H, strips);
+hipError_t launch_upscale(const float* in, int32_t nv, const int32_t* lo_sizes, float* out,
+                          const int32_t* hi_sizes, int32_t band_rows, hipStream_t stream) {
+  if (band_rows <= 0) band_rows = 16;
+  UpParams p{};
+  p.nv = nv;
+  int64_t blocks = 0, in_off = 0, out_off = 0;
+  for (int v = 0; v < nv; ++v) {
+    UpView& u = p.view[v];
+    u.w = lo_sizes[2 * v];
+    u.h = lo_sizes[2 * v + 1];
+    u.W = hi_sizes[2 * v];
+    u.H = hi_sizes[2 * v + 1];
+    u.strips = (int32_t)ceil_div(u.W, kThreads);
+    u.in_off = in_off;
+    u.out_off = out_off;
+    u.blk_off = blocks;
+    blocks += (int64_t)u.strips * ceil_div(u.H, band_rows);
+    in_off += (int64_t)u.w * u.h;
+    out_off += (int64_t)u.W * u.H;
+  }
+  p.blocks = blocks;
+  const unsigned grid = (unsigned)xcd_grid(blocks);
+  switch (band_rows) {
+    case 4: upscale_kernel<4><<<grid, kThreads, 0, stream>>>(p, in, out); break;
+    case 8: upscale_kernel<8><<<grid, kThreads, 0, stream>>>(p, in, out); break;
+    case 16: upscale_kernel<16><<<grid, kThreads, 0, stream>>>(p, in, out); break;
+    case 32: upscale_kernel<32><<<grid, kThreads, 0, stream>>>(p, in, out); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -72,6 +72,31 @@ class Renderer:
         b["n_pairs"] = k
         return k
 
+    def bin_sort_async(self, cam: dict, cfg: dict, b: dict | None = None) -> None:
+        """gs_bin_sort_async: no wait; the pair count lands in b["n_pairs_dev"].
+        Call :meth:`pairs_fit` once the stream has run to see whether the
+        frame fitted the buffers."""
+        b = b or self._view_bufs(cam, cfg)
+        if b["capacity"] == 0:
+            self._ensure_capacity(b, cam, cfg, 4 * self.n + 1024)
+        if "n_pairs_dev" not in b:
+            b["n_pairs_dev"] = torch.zeros(1, dtype=torch.int64, device=self.device)
+        L.gs_bin_sort_async(self.n, b["depth"], b["rect"], cam, cfg, b["capacity"], b["ids"],
+                            b["ranges"], b["n_pairs_dev"], b["workspace"])
+
+    def pairs_fit(self, cam: dict, cfg: dict, b: dict | None = None) -> bool:
+        """After gs_bin_sort_async (waits for the stream): True if the pairs fitted;
+        otherwise grows the buffers for the next frame and returns False."""
+        b = b or self._view_bufs(cam, cfg)
+        k = int(b["n_pairs_dev"].item())
+        b["n_pairs"] = k
+        if k <= b["capacity"]:
+            return True
+        if k >= 2 ** 31:
+            raise L.GsError(L.GS_ERR_CAPACITY, f"{k} pairs exceed the 2^31 index limit", k)
+        self._ensure_capacity(b, cam, cfg, int(k * 1.25) + 1024)
+        return False
+
     def raster(self, cam: dict, cfg: dict, want_grads: bool = True, out=None, n_blend=None, b=None):
         b = b or self._view_bufs(cam, cfg)
         C = 12 if want_grads else 3

@@ -17,6 +17,9 @@ stand in for them with the same Gaussian counts and image sizes):
 * ``scene``     3M Gaussians: 2.4M from the cluster process plus 0.6M on a
                 shell of radius 10 (20 %); same scales, SH and opacity;
                 960x540 rendered, upscaled x2, x3, x4 (up to 3840x2160).
+* ``batch``     1M Gaussians of the ``scene`` process, seen by 8 stereo pairs
+                (16 views, :func:`stereo_rig`): pairs 0-3 at 720x800 upscaled
+                x2 to 1440x1600, pairs 4-7 at 480x540 upscaled x3 to 1440x1620.
 
 Draw order from ``numpy.random.default_rng(seed)``: means, log-scales,
 quaternions, opacity logits, SH coefficients.  Opacity is sigmoid(N(0, 1)).
@@ -31,15 +34,17 @@ WORKLOADS = {
     "tiny": dict(n=10_000, kind="uniform", sh_degree=0, size=(128, 128), scales=(2,), seed=1),
     "clusters": dict(n=500_000, kind="clusters", sh_degree=3, size=(960, 540), scales=(2,), seed=2),
     "scene": dict(n=3_000_000, kind="scene", sh_degree=3, size=(960, 540), scales=(2, 3, 4), seed=3),
+    "batch": dict(n=1_000_000, kind="scene", sh_degree=3, size=None, scales=None, seed=4),
 }
 
 
 def render_config(sh_degree: int, tile_size: int = 16, **over) -> dict:
     """Render settings: tile size, SH degree, dilation (px^2 added to the 2D
-    covariance diagonal), alpha_min (skip), alpha_max (clamp), t_min (stop)
-    and background colour."""
+    covariance diagonal), alpha_min (skip), alpha_max (clamp), t_min (stop),
+    background colour, and the rasterizer's LDS batch (0 = one splat per
+    thread; a speed setting only)."""
     cfg = dict(tile_size=tile_size, sh_degree=sh_degree, dilation=0.3, alpha_min=1.0 / 255.0,
-               alpha_max=0.99, t_min=1e-4, bg=(0.0, 0.0, 0.0))
+               alpha_max=0.99, t_min=1e-4, bg=(0.0, 0.0, 0.0), batch=0)
     cfg.update(over)
     return cfg
 
@@ -158,3 +163,28 @@ def orbit_camera(width: int, height: int, azimuth_deg: float, elevation_deg: flo
 def workload_camera(name: str) -> dict:
     W, H = WORKLOADS[name]["size"]
     return make_camera(W, H)
+
+
+def stereo_rig(n_pairs: int = 8, seed: int = 4, baseline: float = 0.064, radius: float = 3.0):
+    """Stereo pairs on a random orbit around the origin: azimuth ~ U[0, 360),
+    elevation ~ U[-20, 20] degrees, distance ``radius``; the two eyes sit at
+    -/+ baseline/2 along the pair's camera x axis with parallel optical axes.
+    The first half of the pairs renders 720x800 (upscaled x2 to 1440x1600),
+    the second half 480x540 (x3 to 1440x1620).  Returns (low-res cameras,
+    high-res sizes), two entries per pair (left eye first)."""
+    rng = np.random.default_rng(seed)
+    cams, hi = [], []
+    for k in range(n_pairs):
+        a = math.radians(rng.uniform(0.0, 360.0))
+        e = math.radians(rng.uniform(-20.0, 20.0))
+        centre = np.array([radius * math.cos(e) * math.sin(a), -radius * math.sin(e),
+                           -radius * math.cos(e) * math.cos(a)])
+        fwd = -centre / np.linalg.norm(centre)
+        right = np.cross(np.array([0.0, 1.0, 0.0]), fwd)
+        right /= np.linalg.norm(right)
+        (w, h), s = ((720, 800), 2) if k < n_pairs // 2 else ((480, 540), 3)
+        for side in (-0.5, 0.5):
+            eye = centre + side * baseline * right
+            cams.append(make_camera(w, h, eye=tuple(eye), target=tuple(eye + fwd)))
+            hi.append((w * s, h * s))
+    return cams, hi
