@@ -28,6 +28,14 @@
  *                    A = C^-1 F C^-T (Sec. "Image Gradient Based Upscaling",
  *                    Suppl. "Spline Image Interpolation") and its derivatives.
  *   or_upscale       the same patch evaluated at every high-res pixel centre.
+ *   or_upscale_adjoint  transpose of or_upscale: gradient of a loss with
+ *                    respect to the low-res values and derivatives.
+ *   or_composite_adjoint  gradient of a loss on (I, I_x, I_y, I_xy) with respect
+ *                    to every Gaussian's 2D mean, conic, opacity and colour
+ *                    (Suppl. "3DGS Gradient Computation - Backward pass":
+ *                    back-to-front recurrences for B-hat and its derivatives,
+ *                    dI/d alpha_k = T_k (c_k - B-hat_{k+1}) and its screen
+ *                    derivatives, chain rule to the parameters; colour weights).
  *
  * Readings where the paper is silent or garbled (all shared with the HIP path
  * by specification, never by code):
@@ -154,8 +162,8 @@ static void quat_to_rot(double w, double x, double y, double z, double R[3][3]) 
  * A Gaussian is culled (valid = 0) when an input is not finite, when its
  * camera z is at or before the near plane, when the 2D covariance is not
  * positive definite, or when sigma < alpha_min (it can never reach alpha_min). */
-void or_project(int64_t n, const float* means, const float* log_scales, const float* quats,
-                const float* opacity, const float* sh, const or_camera* cam, const or_config* cfg,
+void or_project(int64_t n, const double* means, const double* log_scales, const double* quats,
+                const double* opacity, const double* sh, const or_camera* cam, const or_config* cfg,
                 int32_t* valid, double* mean2d, double* cov2d, double* conic, double* opac,
                 double* rgb, double* depth, double* bbox) {
   const int nb = (cfg->sh_degree + 1) * (cfg->sh_degree + 1);
@@ -538,6 +546,189 @@ void or_upscale(const double* img, int32_t w, int32_t h, int32_t W, int32_t H, i
     free(v);
     free(r);
   }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adjoints (gradients of a loss)                                            */
+/* ------------------------------------------------------------------------- */
+
+/* Gradient of L = sum_p g[p] . upscaled[p] (all W x H output pixels, rgb) with
+ * respect to the low-res buffer [h, w, 12]: every output pixel evaluates
+ * p = X^T C^-1 F C^-T Y, so the weight of F[k][c] is (C^-T X)_k (C^-T Y)_c;
+ * it is added back to the image entry F[k][c] came from.  d_img is overwritten. */
+void or_upscale_adjoint(const double* g, int32_t w, int32_t h, int32_t W, int32_t H,
+                        double* d_img) {
+  double C[4][4], Ci[4][4];
+  build_C(C);
+  invert4(C, Ci);
+  memset(d_img, 0, sizeof(double) * (size_t)w * h * 12);
+  for (int32_t Yp = 0; Yp < H; ++Yp)
+    for (int32_t Xp = 0; Xp < W; ++Xp) {
+      double u = (Xp + 0.5) * (double)w / (double)W - 0.5;
+      double v = (Yp + 0.5) * (double)h / (double)H - 0.5;
+      int i = (int)floor(u), j = (int)floor(v);
+      if (i < 0) i = 0;
+      if (i > w - 2) i = w - 2;
+      if (j < 0) j = 0;
+      if (j > h - 2) j = h - 2;
+      double x = u - i, y = v - j;
+      double X[4] = {1, x, x * x, x * x * x}, Y[4] = {1, y, y * y, y * y * y};
+      double hx[4], hy[4];
+      for (int k = 0; k < 4; ++k) {
+        hx[k] = 0.0;
+        hy[k] = 0.0;
+        for (int r = 0; r < 4; ++r) {
+          hx[k] += Ci[r][k] * X[r];
+          hy[k] += Ci[r][k] * Y[r];
+        }
+      }
+      /* F[k][c]: k = (x offset, value/x-derivative), c = (y offset, value/y-derivative),
+       * laid out as in or_patch_eval: row k -> (ox, qx) = {(0,v),(1,v),(0,d),(1,d)} */
+      static const int kox[4] = {0, 1, 0, 1}, kqd[4] = {0, 0, 1, 1};
+      for (int k = 0; k < 4; ++k)
+        for (int c = 0; c < 4; ++c) {
+          int ox = kox[k], oy = kox[c];
+          int q = kqd[k] + 2 * kqd[c];  /* 0 value, 1 f_x, 2 f_y, 3 f_xy */
+          double wgt = hx[k] * hy[c];
+          double* dst = d_img + (((int64_t)(j + oy) * w + (i + ox)) * 12) + 3 * q;
+          const double* gp = g + 3 * ((int64_t)Yp * W + Xp);
+          for (int ch = 0; ch < 3; ++ch) dst[ch] += wgt * gp[ch];
+        }
+    }
+}
+
+/* Gradient of L = sum_p G[p] . (I, I_x, I_y, I_xy)(px[p], py[p]) with respect
+ * to the 2D parameters of every Gaussian, added to grad[i*9 ..] =
+ * (mean x, mean y, conic a, b, c, opacity sigma, colour r, g, b).
+ * The index set of each point (skips, clamps, stop) is that of the plain walk
+ * and is held fixed; a clamped fragment (alpha = alpha_max) has no geometric
+ * or opacity gradient.  The background enters as a last fragment of colour bg
+ * and alpha 1, i.e. B-hat_{N+1} = bg. */
+void or_composite_adjoint(int64_t m, const int64_t* order, const double* mean2d,
+                          const double* conic, const double* opac, const double* rgb,
+                          const or_config* cfg, int64_t npts, const double* px, const double* py,
+                          const double* G, double* grad) {
+  /* per blended fragment of one walk */
+  int64_t* fi = (int64_t*)malloc(sizeof(int64_t) * (m > 0 ? m : 1));
+  double* fs = (double*)malloc(sizeof(double) * 12 * (m > 0 ? m : 1));
+  for (int64_t p = 0; p < npts; ++p) {
+    const double x = px[p], y = py[p];
+    const double* Gp = G + 12 * p;
+    /* forward walk (front to back), recording alpha, its derivatives, and
+     * A_{k-1} with its derivatives before each blend */
+    double A = 0.0, Ax = 0.0, Ay = 0.0, Axy = 0.0;
+    int64_t nf = 0;
+    for (int64_t k = 0; k < m; ++k) {
+      int64_t i = order[k];
+      double dx = x - mean2d[2 * i], dy = y - mean2d[2 * i + 1];
+      double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
+      double g = -0.5 * (a * dx * dx + 2.0 * b * dx * dy + c * dy * dy);
+      double gx = -(a * dx + b * dy), gy = -(b * dx + c * dy), gxy = -b;
+      double alpha = opac[i] * exp(g);
+      if (alpha < cfg->alpha_min) continue;
+      int clamp = alpha > cfg->alpha_max;
+      double ax, ay, axy;
+      if (clamp) {
+        alpha = cfg->alpha_max;
+        ax = ay = axy = 0.0;
+      } else {
+        ax = alpha * gx;
+        ay = alpha * gy;
+        axy = alpha * (gx * gy + gxy);
+      }
+      double* st = fs + 12 * nf;
+      st[0] = alpha; st[1] = ax; st[2] = ay; st[3] = axy;
+      st[4] = A; st[5] = Ax; st[6] = Ay; st[7] = Axy;
+      st[8] = clamp; st[9] = dx; st[10] = dy; st[11] = 0.0;
+      fi[nf++] = i;
+      double T = 1.0 - A;
+      double Axy_n = Axy * (1.0 - alpha) + T * axy - Ax * ay - Ay * ax;
+      double Ax_n = Ax * (1.0 - alpha) + T * ax;
+      double Ay_n = Ay * (1.0 - alpha) + T * ay;
+      A = A + alpha * T;
+      Ax = Ax_n;
+      Ay = Ay_n;
+      Axy = Axy_n;
+      if (1.0 - A < cfg->t_min) break;
+    }
+    /* backward walk (back to front): B-hat_{k+1} and its derivatives */
+    double Bh[3], Bhx[3] = {0, 0, 0}, Bhy[3] = {0, 0, 0}, Bhxy[3] = {0, 0, 0};
+    for (int ch = 0; ch < 3; ++ch) Bh[ch] = cfg->bg[ch];
+    for (int64_t f = nf - 1; f >= 0; --f) {
+      const int64_t i = fi[f];
+      const double* st = fs + 12 * f;
+      const double alpha = st[0], ax = st[1], ay = st[2], axy = st[3];
+      const double Ak = st[4], Akx = st[5], Aky = st[6], Akxy = st[7];
+      const int clamp = st[8] != 0.0;
+      const double dx = st[9], dy = st[10];
+      const double T = 1.0 - Ak;
+      /* colour: weights of c_k in I, I_x, I_y, I_xy */
+      const double w0 = T * alpha, wx = T * ax - Akx * alpha, wy = T * ay - Aky * alpha;
+      const double wxy = T * axy - Akx * ay - Aky * ax - Akxy * alpha;
+      for (int ch = 0; ch < 3; ++ch)
+        grad[9 * i + 6 + ch] += Gp[ch] * w0 + Gp[3 + ch] * wx + Gp[6 + ch] * wy + Gp[9 + ch] * wxy;
+      if (!clamp) {
+        /* dI/d alpha_k = T_k (c_k - B-hat_{k+1}) and its screen derivatives */
+        double P[3], Px[3], Py[3], Pxy[3];
+        for (int ch = 0; ch < 3; ++ch) {
+          const double e = rgb[3 * i + ch] - Bh[ch];
+          P[ch] = T * e;
+          Px[ch] = -Akx * e - T * Bhx[ch];
+          Py[ch] = -Aky * e - T * Bhy[ch];
+          Pxy[ch] = -Akxy * e - T * Bhxy[ch] + Akx * Bhy[ch] + Aky * Bhx[ch];
+        }
+        /* alpha = sigma e^g and the derivatives of alpha, alpha_x, alpha_y,
+         * alpha_xy with respect to (mean x, mean y, a, b, c, sigma) */
+        const double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
+        const double gx = -(a * dx + b * dy), gy = -(b * dx + c * dy), gxy = -b;
+        /* g_theta, gx_theta, gy_theta, gxy_theta */
+        const double dg[5][4] = {
+            {a * dx + b * dy, a, b, 0.0},        /* mean x: d(dx) = -1 */
+            {b * dx + c * dy, b, c, 0.0},        /* mean y */
+            {-0.5 * dx * dx, -dx, 0.0, 0.0},     /* a */
+            {-dx * dy, -dy, -dx, -1.0},          /* b */
+            {-0.5 * dy * dy, 0.0, -dy, 0.0},     /* c */
+        };
+        for (int t = 0; t < 6; ++t) {
+          double at, axt, ayt, axyt;
+          if (t < 5) {
+            at = alpha * dg[t][0];
+            axt = at * gx + alpha * dg[t][1];
+            ayt = at * gy + alpha * dg[t][2];
+            axyt = at * (gx * gy + gxy) + alpha * (dg[t][1] * gy + gx * dg[t][2] + dg[t][3]);
+          } else {
+            const double sg = opac[i];
+            at = alpha / sg;
+            axt = ax / sg;
+            ayt = ay / sg;
+            axyt = axy / sg;
+          }
+          double acc = 0.0;
+          for (int ch = 0; ch < 3; ++ch) {
+            acc += Gp[ch] * (P[ch] * at);
+            acc += Gp[3 + ch] * (Px[ch] * at + P[ch] * axt);
+            acc += Gp[6 + ch] * (Py[ch] * at + P[ch] * ayt);
+            acc += Gp[9 + ch] * (Pxy[ch] * at + Px[ch] * ayt + Py[ch] * axt + P[ch] * axyt);
+          }
+          grad[9 * i + t] += acc;
+        }
+      }
+      /* B-hat_k from B-hat_{k+1} */
+      for (int ch = 0; ch < 3; ++ch) {
+        const double ci = rgb[3 * i + ch];
+        const double e = ci - Bh[ch];
+        const double nBxy = (1.0 - alpha) * Bhxy[ch] + axy * e - ay * Bhx[ch] - ax * Bhy[ch];
+        const double nBx = (1.0 - alpha) * Bhx[ch] + ax * e;
+        const double nBy = (1.0 - alpha) * Bhy[ch] + ay * e;
+        Bh[ch] = (1.0 - alpha) * Bh[ch] + alpha * ci;
+        Bhx[ch] = nBx;
+        Bhy[ch] = nBy;
+        Bhxy[ch] = nBxy;
+      }
+    }
+  }
+  free(fi);
+  free(fs);
 }
 
 int32_t or_max_variants(void) { return OR_MAX_VAR; }

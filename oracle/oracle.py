@@ -18,6 +18,12 @@ holds the arithmetic):
                        Based Upscaling"; Suppl. "Spline Image Interpolation").
 * ``tile_rects`` / ``tile_lists`` -- the tiling that an accelerated renderer may
                        use; it must not change the composited result.
+* ``upscale_adjoint`` / ``composite_adjoint`` / ``project_vjp`` / ``loss_grad``
+                    -- gradients of a loss on the upscaled image with respect
+                       to the low-res buffers, the 2D splat parameters and the
+                       3D Gaussian parameters (Suppl. "3DGS Gradient Computation -
+                       Backward pass"; the projection's Jacobian by FP64 central
+                       differences of ``project``).
 """
 from __future__ import annotations
 
@@ -78,10 +84,12 @@ def _load():
         lib.or_hermite_matrices.argtypes = [P, P]
         lib.or_patch_eval.argtypes = [P, i32, i32, i64, P, P, P]
         lib.or_upscale.argtypes = [P, i32, i32, i32, i32, i64, P, P, P]
+        lib.or_upscale_adjoint.argtypes = [P, i32, i32, i32, i32, P]
+        lib.or_composite_adjoint.argtypes = [i64, P, P, P, P, P, P, i64, P, P, P, P]
         lib.or_max_variants.restype = i32
         lib.or_num_threads.restype = i32
         for f in ("or_sh_basis", "or_project", "or_composite", "or_hermite_matrices",
-                  "or_patch_eval", "or_upscale"):
+                  "or_patch_eval", "or_upscale", "or_upscale_adjoint", "or_composite_adjoint"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -127,10 +135,11 @@ def sh_basis(deg: int, dirs: np.ndarray) -> np.ndarray:
 
 
 def project(scene: dict, cam: dict, cfg: dict) -> dict:
-    """FP64 projection of every Gaussian of ``scene`` (FP32 arrays) into ``cam``."""
+    """FP64 projection of every Gaussian of ``scene`` (FP32 or FP64 arrays) into ``cam``."""
     n = scene["means"].shape[0]
-    f32 = lambda k: np.ascontiguousarray(scene[k], np.float32)
-    means, ls, quats, opa, sh = f32("means"), f32("log_scales"), f32("quats"), f32("opacity"), f32("sh")
+    # FP32 scene values promote exactly; FP64 values (finite differences) pass as they are
+    f64 = lambda k: np.ascontiguousarray(scene[k], np.float64)
+    means, ls, quats, opa, sh = f64("means"), f64("log_scales"), f64("quats"), f64("opacity"), f64("sh")
     assert sh.shape[1] == (cfg["sh_degree"] + 1) ** 2
     out = dict(valid=np.empty(n, np.int32), mean2d=np.empty((n, 2)), cov2d=np.empty((n, 3)),
                conic=np.empty((n, 3)), opacity=np.empty(n), rgb=np.empty((n, 3)),
@@ -322,3 +331,87 @@ def fd_slopes(img: np.ndarray) -> np.ndarray:
 
     fx = d(f, 1)
     return np.concatenate([f, fx, d(f, 0), d(fx, 0)], axis=2)
+
+
+# ---------------------------------------------------------------------------
+# Gradients.  A loss L on the upscaled image reaches the Gaussians through the
+# upscaler (linear: its adjoint is the transpose), the compositing (adjoint of
+# the blend with the index set of every pixel held fixed) and the projection.
+# ---------------------------------------------------------------------------
+SPLAT_GRAD = ("mean_x", "mean_y", "conic_a", "conic_b", "conic_c", "opacity", "r", "g", "b")
+
+
+def upscale_adjoint(g: np.ndarray, w: int, h: int) -> np.ndarray:
+    """dL/d(low-res [h, w, 12]) for dL/d(upscaled [H, W, 3]) = g."""
+    g = np.ascontiguousarray(g, np.float64)
+    H, W = g.shape[:2]
+    out = np.empty((h, w, 12))
+    _load().or_upscale_adjoint(_ptr(g), w, h, W, H, _ptr(out))
+    return out
+
+
+def composite_adjoint(proj: dict, order: np.ndarray, cfg: dict, px, py, G) -> np.ndarray:
+    """dL/d(2D parameters) [n, 9] (columns ``SPLAT_GRAD``) for
+    L = sum_p G[p] . composite(px[p], py[p]) (G [npts, 12])."""
+    px = np.ascontiguousarray(px, np.float64).reshape(-1)
+    py = np.ascontiguousarray(py, np.float64).reshape(-1)
+    G = np.ascontiguousarray(G, np.float64).reshape(-1, 12)
+    assert G.shape[0] == px.shape[0]
+    n = proj["mean2d"].shape[0]
+    grad = np.zeros((n, 9))
+    order = np.ascontiguousarray(order, np.int64)
+    args = [np.ascontiguousarray(proj[k], np.float64) for k in ("mean2d", "conic", "opacity", "rgb")]
+    k = _config(cfg)
+    _load().or_composite_adjoint(order.shape[0], _ptr(order), *[_ptr(a) for a in args], ctypes.byref(k),
+                                 px.shape[0], _ptr(px), _ptr(py), _ptr(G), _ptr(grad))
+    return grad
+
+
+PARAMS = ("means", "log_scales", "quats", "opacity", "sh")
+
+
+def project_vjp(scene: dict, cam: dict, cfg: dict, d2d: np.ndarray, h: float = 1e-6) -> dict:
+    """dL/d(3D parameters) for dL/d(2D parameters) = d2d [n, 9] in one view:
+    the projection's Jacobian by FP64 central differences (every Gaussian's
+    projection depends on its own parameters only, so one pair of projections
+    per parameter slot serves all Gaussians)."""
+    base = {k: np.asarray(scene[k], np.float64) for k in PARAMS}
+    d2d = np.asarray(d2d, np.float64)
+
+    def outputs(sc):
+        pr = project(dict(sc, sh_degree=scene.get("sh_degree")), cam, cfg)
+        return np.concatenate([pr["mean2d"], pr["conic"], pr["opacity"][:, None], pr["rgb"]], 1)
+
+    grads = {}
+    for k in PARAMS:
+        arr = base[k]
+        g = np.zeros_like(arr)
+        flat = arr.reshape(arr.shape[0], -1)
+        gflat = g.reshape(arr.shape[0], -1)
+        for j in range(flat.shape[1]):
+            step = h * np.maximum(1.0, np.abs(flat[:, j]))
+            up = flat.copy()
+            dn = flat.copy()
+            up[:, j] += step
+            dn[:, j] -= step
+            o_up = outputs(dict(base, **{k: up.reshape(arr.shape)}))
+            o_dn = outputs(dict(base, **{k: dn.reshape(arr.shape)}))
+            gflat[:, j] = ((o_up - o_dn) * d2d).sum(1) / (2 * step)
+        grads[k] = g
+    return grads
+
+
+def loss_grad(scene: dict, cams, hi_sizes, cfg: dict, g_up) -> dict:
+    """dL/d(3D parameters) of L = sum_v g_up[v] . upscaled_v, summed over the
+    views (cams[v] renders, hi_sizes[v] = (W, H) is its upscaled size)."""
+    total = {k: np.zeros(np.shape(scene[k])) for k in PARAMS}
+    for cam, (W, H), g in zip(cams, hi_sizes, g_up):
+        w, h = int(cam["width"]), int(cam["height"])
+        proj = project(scene, cam, cfg)
+        order = depth_order(proj)
+        G = upscale_adjoint(np.asarray(g).reshape(H, W, 3), w, h)
+        yy, xx = np.meshgrid(np.arange(h, dtype=np.float64), np.arange(w, dtype=np.float64), indexing="ij")
+        d2d = composite_adjoint(proj, order, cfg, xx.reshape(-1), yy.reshape(-1), G.reshape(-1, 12))
+        for k, v in project_vjp(scene, cam, cfg, d2d).items():
+            total[k] += v
+    return total
