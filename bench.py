@@ -62,6 +62,8 @@ WORKLOADS = {  # (scene, x factor, y factor); fractional and per-axis factors us
     "clusters_x2": ("clusters", 2, 2), "tiny_x2": ("tiny", 2, 2),
     # 1M Gaussians, 8 stereo pairs: 4 at 720x800 -> 1440x1600, 4 at 480x540 -> 1440x1620
     "stereo16": ("batch", None, None),
+    # training step: 1M Gaussians, 4 views 480x270 -> 1920x1080, forward + L1 loss + backward
+    "train4": ("train", None, None),
 }
 
 
@@ -325,6 +327,106 @@ def run_batch(args):
                 up_gbs=up_bytes / (st[3] * 1e-3) / 1e9, up_bytes=up_bytes, out_px=out_px)
 
 
+def run_train(args):
+    """One training step per timed iteration: the differentiable chain's
+    forward, an L1 loss against direct 1080p renders of a perturbed copy of
+    the scene (means + N(0, 0.01)), and the hand-written backward to every
+    Gaussian parameter."""
+    import torch
+
+    from paper_2503_14171_amd import _lib as L
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.batch import ViewBatch
+    from paper_2503_14171_amd.render import Renderer
+    from paper_2503_14171_amd.train import TrainViews, UpscaledRender
+
+    torch.cuda.set_device(0)
+    sc = scenes.workload_scene("batch")
+    rng = np.random.default_rng(5)
+    cams = [scenes.orbit_camera(480, 270, a, e) for a, e in ((0.0, 5.0), (60.0, -10.0), (150.0, 15.0),
+                                                             (250.0, -5.0))]
+    hi = [(1920, 1080)] * 4
+    cfg = scenes.render_config(sc["sh_degree"])
+    pert = dict(sc, means=(sc["means"] + rng.normal(0, 0.01, sc["means"].shape)).astype(np.float32))
+    tgt = ViewBatch(Renderer(pert), cams, hi, cfg, direct=True)
+    tgt.render()
+    target = tgt.up.clone()
+    del tgt
+    rd = Renderer(sc)
+    params = {k: getattr(rd, k).clone().requires_grad_(True) for k in
+              ("means", "log_scales", "quats", "opacity", "sh")}
+    tv = TrainViews(rd.n, cams, hi, cfg)
+
+    def step():
+        for p_ in params.values():
+            p_.grad = None
+        up = UpscaledRender.apply(params["means"], params["log_scales"], params["quats"],
+                                  params["opacity"], params["sh"], tv)
+        loss = (up - target).abs().mean()
+        loss.backward()
+        return loss
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    # stage times of one step, eager with events
+    r = {k: v.detach() for k, v in params.items()}
+    ev = _events(torch, 8)
+    ev[0].record()
+    L.gs_project_views(r["means"], r["log_scales"], r["quats"], r["opacity"], r["sh"], tv.cams, tv.cfg,
+                       tv.splats, tv.depth, tv.rect)
+    ev[1].record()
+    L.gs_bin_sort_views(tv.n, tv.cams, tv.cfg, tv.depth, tv.rect, tv.capacity, tv.ids, tv.ranges,
+                        tv.n_pairs, tv.workspace)
+    ev[2].record()
+    L.gs_raster_grad_views_train(tv.splats, tv.ids, tv.ranges, tv.cams, tv.cfg, tv.low, tv.state, tv.last)
+    ev[3].record()
+    up = torch.empty((tv.hi_px, 3), dtype=torch.float32, device="cuda")
+    L.gs_upscale_hermite_views(tv.low, tv.lo, up, tv.hi)
+    ev[4].record()
+    d_up = torch.sign(up - target) / up.numel()
+    ev[5].record()
+    L.gs_upscale_hermite_backward_views(d_up, tv.lo, tv.d_low, tv.hi)
+    ev[6].record()
+    L.gs_raster_grad_backward_views(tv.splats, tv.ids, tv.ranges, tv.cams, tv.cfg, tv.state, tv.last,
+                                    tv.d_low, tv.n, tv.d_splats)
+    ev[7].record()
+    g = [torch.empty_like(t) for t in r.values()]
+    e8 = _events(torch, 2)
+    e8[0].record()
+    L.gs_project_backward_views(r["means"], r["log_scales"], r["quats"], r["opacity"], r["sh"], tv.cams,
+                                tv.cfg, tv.d_splats, *g)
+    e8[1].record()
+    torch.cuda.synchronize()
+    st = {"project": ev[0].elapsed_time(ev[1]), "bin_sort": ev[1].elapsed_time(ev[2]),
+          "raster_grad_fwd": ev[2].elapsed_time(ev[3]), "upscale_fwd": ev[3].elapsed_time(ev[4]),
+          "upscale_bwd": ev[5].elapsed_time(ev[6]), "raster_grad_bwd": ev[6].elapsed_time(ev[7]),
+          "project_bwd": e8[0].elapsed_time(e8[1])}
+    out_px = sum(W * H for (W, H) in hi)
+    return dict(n=rd.n, ms=ms, loss=float(loss.item()), stages=st, out_px=out_px,
+                value=out_px / (ms * 1e-3) / 1e6, pairs=int(tv.n_pairs.item()))
+
+
+def train_line(args, res):
+    return {
+        "metric": METRIC, "value": round(res["value"], 2), "unit": "Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"training step: {res['n']} Gaussians, SH degree 3, 4 views 480x270 rendered "
+                               "with gradients and upscaled x4 to 1920x1080, L1 loss against direct 1080p "
+                               "renders of the scene with means + N(0, 0.01), backward to all parameters",
+                   "gaussians": res["n"], "views": 4, "output_pixels": res["out_px"]},
+        "stages_ms": {k: round(v, 4) for k, v in res["stages"].items()},
+        "loss": round(res["loss"], 6), "pairs": res["pairs"],
+    }
+
+
 def batch_line(args, res):
     tuned = res["tuned"]
     return {
@@ -424,6 +526,10 @@ def main():
     if WORKLOADS[args.workload][0] == "batch":
         res = run_batch(args)
         print(json.dumps(batch_line(args, res)), flush=True)
+        return
+    if WORKLOADS[args.workload][0] == "train":
+        res = run_train(args)
+        print(json.dumps(train_line(args, res)), flush=True)
         return
     res = run_gpu(args)
     if args.copy_probe_mb:

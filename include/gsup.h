@@ -257,6 +257,57 @@ gs_status gs_upscale_hermite_views(const float* in, int32_t n_views, const int32
                                    float* out, const int32_t* hi_sizes, int32_t band_rows,
                                    void* stream);
 
+/* ---- Backward pass (training through the upscaler) --------------------------
+ * Sec. "Image Gradient Based Upscaling" (Differentiable Image Gradients) and
+ * Suppl. "3DGS Gradient Computation - Backward pass" (back-to-front blending,
+ * dI/d alpha_k and its screen derivatives, colour gradients, inversion trick).
+ * A training step: gs_project_views, gs_bin_sort_views,
+ * gs_raster_grad_views_train, gs_upscale_hermite_views; then, with
+ * dL/d(upscaled), gs_upscale_hermite_backward_views, gs_raster_grad_backward_views,
+ * gs_project_backward_views.  The index set of every pixel (skips, clamps,
+ * stop) is the forward's and is held fixed; a clamped fragment has no
+ * geometric gradient; a colour clamped at zero has none either. */
+
+/* Forward with gradients (as gs_raster_grad_views with want_grads = 1) that
+ * also saves, per low-res pixel, state [pix, 4] = final (T, T_x, T_y, T_xy)
+ * (device, 16-byte aligned) and last [pix] (int32) = the position in
+ * sorted_ids after the pixel's last blended fragment.  Both feed
+ * gs_raster_grad_backward_views. */
+gs_status gs_raster_grad_views_train(const gs_splat* splats, const int32_t* sorted_ids,
+                                     const int32_t* tile_ranges, int32_t n_views,
+                                     const gs_camera* cams, const gs_raster_cfg* cfg, float* out,
+                                     float* state, int32_t* last, void* stream);
+
+/* Adjoint of gs_upscale_hermite_views: d_out [sum H W, 3] = dL/d(upscaled) ->
+ * d_in [sum h w, 12] = dL/d(low-res values and derivatives), overwritten.
+ * Deterministic (no atomics).  d_in 16-byte aligned, no overlap. */
+gs_status gs_upscale_hermite_backward_views(const float* d_out, int32_t n_views,
+                                            const int32_t* lo_sizes, float* d_in,
+                                            const int32_t* hi_sizes, void* stream);
+
+/* d_lowres [sum h w, 12] = dL/d(I, I_x, I_y, I_xy) -> d_splats [n_views * n, 9]
+ * (overwritten) = dL/d(mean x, mean y, conic a, b, c, opacity, r, g, b) of every
+ * splat record, from the buffers of the matching forward (same splats, lists,
+ * state and last).  The state before each fragment is recovered by inverting
+ * the blend; contributions are summed with atomics (order not fixed, so the
+ * last bits may vary between runs). */
+gs_status gs_raster_grad_backward_views(const gs_splat* splats, const int32_t* sorted_ids,
+                                        const int32_t* tile_ranges, int32_t n_views,
+                                        const gs_camera* cams, const gs_raster_cfg* cfg,
+                                        const float* state, const int32_t* last,
+                                        const float* d_lowres, int64_t n, float* d_splats,
+                                        void* stream);
+
+/* d_splats [n_views * n, 9] -> dL/d(means [n,3], log_scales [n,3], quats [n,4]
+ * (16-byte aligned), opacity [n], sh [n,(d+1)^2,3]), summed over the views,
+ * overwritten.  Records with an all-zero gradient are skipped. */
+gs_status gs_project_backward_views(int64_t n, const float* means, const float* log_scales,
+                                    const float* quats, const float* opacity, const float* sh,
+                                    int32_t n_views, const gs_camera* cams,
+                                    const gs_raster_cfg* cfg, const float* d_splats,
+                                    float* d_means, float* d_log_scales, float* d_quats,
+                                    float* d_opacity, float* d_sh, void* stream);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char* gs_last_error_message(void);
 

@@ -85,6 +85,14 @@ def lib() -> ctypes.CDLL:
         L.gs_raster_grad_views.restype = ctypes.c_int
         L.gs_upscale_hermite_views.argtypes = [P, i32, ctypes.POINTER(i32), P, ctypes.POINTER(i32), i32, P]
         L.gs_upscale_hermite_views.restype = ctypes.c_int
+        L.gs_raster_grad_views_train.argtypes = [P, P, P, i32, cams_p, cfg_p, P, P, P, P]
+        L.gs_raster_grad_views_train.restype = ctypes.c_int
+        L.gs_upscale_hermite_backward_views.argtypes = [P, i32, ctypes.POINTER(i32), P, ctypes.POINTER(i32), P]
+        L.gs_upscale_hermite_backward_views.restype = ctypes.c_int
+        L.gs_raster_grad_backward_views.argtypes = [P, P, P, i32, cams_p, cfg_p, P, P, P, i64, P, P]
+        L.gs_raster_grad_backward_views.restype = ctypes.c_int
+        L.gs_project_backward_views.argtypes = [i64, P, P, P, P, P, i32, cams_p, cfg_p, P, P, P, P, P, P, P]
+        L.gs_project_backward_views.restype = ctypes.c_int
         L.gs_fd_slopes.argtypes = [P, i32, i32, P, P]
         L.gs_fd_slopes.restype = ctypes.c_int
         L.gs_last_error_message.restype = ctypes.c_char_p
@@ -262,3 +270,42 @@ def gs_upscale_hermite_views(inp, lo_sizes, out, hi_sizes, band_rows: int = 0, s
     hi = (ctypes.c_int32 * (2 * nv))(*[int(v) for wh in hi_sizes for v in wh])
     _check(lib().gs_upscale_hermite_views(_ptr(inp, torch.float32), nv, lo, _ptr(out, torch.float32), hi,
                                           band_rows, _stream(stream)))
+
+
+# ---- backward ----------------------------------------------------------------
+def _sizes(sizes):
+    nv = len(sizes)
+    return (ctypes.c_int32 * (2 * nv))(*[int(v) for wh in sizes for v in wh])
+
+
+def gs_raster_grad_views_train(splats, sorted_ids, tile_ranges, cams, cfg: dict, out, state, last,
+                               stream=None) -> None:
+    """Forward with gradients that also saves state [pix, 4] and last [pix] for the backward."""
+    _check(lib().gs_raster_grad_views_train(_ptr(splats, torch.float32), _ptr(sorted_ids, torch.int32),
+                                            _ptr(tile_ranges, torch.int32), len(cams), cameras(cams),
+                                            ctypes.byref(raster_cfg(cfg)), _ptr(out, torch.float32),
+                                            _ptr(state, torch.float32), _ptr(last, torch.int32), _stream(stream)))
+
+
+def gs_upscale_hermite_backward_views(d_out, lo_sizes, d_in, hi_sizes, stream=None) -> None:
+    _check(lib().gs_upscale_hermite_backward_views(_ptr(d_out, torch.float32), len(lo_sizes), _sizes(lo_sizes),
+                                                   _ptr(d_in, torch.float32), _sizes(hi_sizes), _stream(stream)))
+
+
+def gs_raster_grad_backward_views(splats, sorted_ids, tile_ranges, cams, cfg: dict, state, last, d_lowres,
+                                  n: int, d_splats, stream=None) -> None:
+    _check(lib().gs_raster_grad_backward_views(_ptr(splats, torch.float32), _ptr(sorted_ids, torch.int32),
+                                               _ptr(tile_ranges, torch.int32), len(cams), cameras(cams),
+                                               ctypes.byref(raster_cfg(cfg)), _ptr(state, torch.float32),
+                                               _ptr(last, torch.int32), _ptr(d_lowres, torch.float32), n,
+                                               _ptr(d_splats, torch.float32), _stream(stream)))
+
+
+def gs_project_backward_views(means, log_scales, quats, opacity, sh, cams, cfg: dict, d_splats, d_means,
+                              d_log_scales, d_quats, d_opacity, d_sh, stream=None) -> None:
+    f = torch.float32
+    _check(lib().gs_project_backward_views(means.shape[0], _ptr(means, f), _ptr(log_scales, f), _ptr(quats, f),
+                                           _ptr(opacity, f), _ptr(sh, f), len(cams), cameras(cams),
+                                           ctypes.byref(raster_cfg(cfg)), _ptr(d_splats, f), _ptr(d_means, f),
+                                           _ptr(d_log_scales, f), _ptr(d_quats, f), _ptr(d_opacity, f),
+                                           _ptr(d_sh, f), _stream(stream)))

@@ -199,7 +199,7 @@ gs_status raster_impl(const char* fn, const gs_splat* splats, const int32_t* sor
   if (total_tiles(nv, cams, cfg->tile_size) >= (int64_t(1) << 31))
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: too many tiles", fn);
   return check_hip(launch_raster(splats, sorted_ids, tile_ranges, nv, cams, *cfg, want_grads != 0,
-                                 out, n_blend, static_cast<hipStream_t>(stream)),
+                                 out, n_blend, nullptr, nullptr, static_cast<hipStream_t>(stream)),
                    "raster launch");
 }
 
@@ -364,6 +364,107 @@ gs_status gs_fd_slopes(const float* img, int32_t w, int32_t h, float* out, void*
   if (ib < oe && ob < ie) return fail(GS_ERR_INVALID_ARGUMENT, "%s: img and out overlap", fn);
   return check_hip(launch_fd_slopes(img, w, h, out, static_cast<hipStream_t>(stream)),
                    "gs_fd_slopes launch");
+}
+
+// ---- backward ----------------------------------------------------------------
+
+gs_status gs_raster_grad_views_train(const gs_splat* splats, const int32_t* sorted_ids,
+                                     const int32_t* tile_ranges, int32_t n_views,
+                                     const gs_camera* cams, const gs_raster_cfg* cfg, float* out,
+                                     float* state, int32_t* last, void* stream) {
+  g_msg[0] = 0;
+  const char* fn = "gs_raster_grad_views_train";
+  GS_CHECK(check_views(fn, n_views, cams));
+  GS_CHECK(check_cfg(fn, cfg));
+  if (!splats || !sorted_ids || !tile_ranges || !out || !state || !last)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
+  if (!aligned(splats, 16) || !aligned(tile_ranges, 8) || !aligned(out, 16) ||
+      !aligned(state, 16) || !aligned(last, 4) || !aligned(sorted_ids, 4))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: splats, out and state must be 16-byte aligned", fn);
+  return check_hip(launch_raster(splats, sorted_ids, tile_ranges, n_views, cams, *cfg, true, out,
+                                 nullptr, state, last, static_cast<hipStream_t>(stream)),
+                   "raster launch");
+}
+
+gs_status gs_upscale_hermite_backward_views(const float* d_out, int32_t n_views,
+                                            const int32_t* lo_sizes, float* d_in,
+                                            const int32_t* hi_sizes, void* stream) {
+  g_msg[0] = 0;
+  const char* fn = "gs_upscale_hermite_backward_views";
+  if (!d_out || !d_in || !lo_sizes || !hi_sizes)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
+  if (n_views < 1 || n_views > GS_MAX_VIEWS)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n_views %d outside [1, %d]", fn, n_views,
+                GS_MAX_VIEWS);
+  int64_t in_px = 0, out_px = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const int32_t w = lo_sizes[2 * v], h = lo_sizes[2 * v + 1];
+    const int32_t W = hi_sizes[2 * v], H = hi_sizes[2 * v + 1];
+    if (w < 2 || h < 2 || w > kMaxSide || h > kMaxSide || W < w || H < h || W > 4 * kMaxSide ||
+        H > 4 * kMaxSide)
+      return fail(GS_ERR_INVALID_ARGUMENT, "%s: view %d sizes %d x %d -> %d x %d invalid", fn, v,
+                  w, h, W, H);
+    in_px += (int64_t)w * h;
+    out_px += (int64_t)W * H;
+  }
+  if (!aligned(d_in, 16) || !aligned(d_out, 4))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: d_in must be 16-byte aligned", fn);
+  const char* ib = reinterpret_cast<const char*>(d_in);
+  const char* ie = ib + (size_t)in_px * 12 * sizeof(float);
+  const char* ob = reinterpret_cast<const char*>(d_out);
+  const char* oe = ob + (size_t)out_px * 3 * sizeof(float);
+  if (ib < oe && ob < ie) return fail(GS_ERR_INVALID_ARGUMENT, "%s: d_in and d_out overlap", fn);
+  return check_hip(launch_upscale_backward(d_out, n_views, lo_sizes, d_in, hi_sizes,
+                                           static_cast<hipStream_t>(stream)),
+                   "upscale backward launch");
+}
+
+gs_status gs_raster_grad_backward_views(const gs_splat* splats, const int32_t* sorted_ids,
+                                        const int32_t* tile_ranges, int32_t n_views,
+                                        const gs_camera* cams, const gs_raster_cfg* cfg,
+                                        const float* state, const int32_t* last,
+                                        const float* d_lowres, int64_t n, float* d_splats,
+                                        void* stream) {
+  g_msg[0] = 0;
+  const char* fn = "gs_raster_grad_backward_views";
+  GS_CHECK(check_views(fn, n_views, cams));
+  GS_CHECK(check_cfg(fn, cfg));
+  if (n < 0 || n * n_views >= (int64_t(1) << 31))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n * n_views outside [0, 2^31)", fn);
+  if (!splats || !sorted_ids || !tile_ranges || !state || !last || !d_lowres || !d_splats)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
+  if (!aligned(splats, 16) || !aligned(tile_ranges, 8) || !aligned(state, 16) ||
+      !aligned(d_lowres, 16) || !aligned(d_splats, 4) || !aligned(last, 4))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: splats, state and d_lowres must be 16-byte aligned",
+                fn);
+  return check_hip(launch_raster_backward(splats, sorted_ids, tile_ranges, n_views, cams, *cfg,
+                                          state, last, d_lowres, n * n_views, d_splats,
+                                          static_cast<hipStream_t>(stream)),
+                   "raster backward launch");
+}
+
+gs_status gs_project_backward_views(int64_t n, const float* means, const float* log_scales,
+                                    const float* quats, const float* opacity, const float* sh,
+                                    int32_t n_views, const gs_camera* cams,
+                                    const gs_raster_cfg* cfg, const float* d_splats,
+                                    float* d_means, float* d_log_scales, float* d_quats,
+                                    float* d_opacity, float* d_sh, void* stream) {
+  g_msg[0] = 0;
+  const char* fn = "gs_project_backward_views";
+  GS_CHECK(check_views(fn, n_views, cams));
+  GS_CHECK(check_cfg(fn, cfg));
+  if (n < 0 || n * n_views >= (int64_t(1) << 31))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: n * n_views outside [0, 2^31)", fn);
+  if (n == 0) return GS_OK;
+  if (!means || !log_scales || !quats || !opacity || !sh || !d_splats || !d_means ||
+      !d_log_scales || !d_quats || !d_opacity || !d_sh)
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
+  if (!aligned(quats, 16) || !aligned(d_quats, 16))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: quats and d_quats must be 16-byte aligned", fn);
+  return check_hip(launch_project_backward(n, means, log_scales, quats, opacity, sh, n_views, cams,
+                                           *cfg, d_splats, d_means, d_log_scales, d_quats,
+                                           d_opacity, d_sh, static_cast<hipStream_t>(stream)),
+                   "projection backward launch");
 }
 
 }  // extern "C"

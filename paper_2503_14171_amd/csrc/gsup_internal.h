@@ -37,6 +37,13 @@ hipError_t launch_project(int64_t n, const float* means, const float* log_scales
                           const gs_camera* cams, const gs_raster_cfg& cfg, gs_splat* splats,
                           float* depth, int32_t* rect, hipStream_t stream);
 
+hipError_t launch_project_backward(int64_t n, const float* means, const float* log_scales,
+                                   const float* quats, const float* opacity, const float* sh,
+                                   int32_t nv, const gs_camera* cams, const gs_raster_cfg& cfg,
+                                   const float* dsplat, float* d_means, float* d_log_scales,
+                                   float* d_quats, float* d_opacity, float* d_sh,
+                                   hipStream_t stream);
+
 // ---- binning and sorting (binsort.hip) --------------------------------------
 // Tile grids of the views of a batch; view v's tiles have the global ids
 // tile_off[v] .. tile_off[v+1) (row-major inside the view).
@@ -76,15 +83,25 @@ gs_status run_bin_sort(const BinSortPlan& plan, const ViewTiles& vt, const float
 // ---- rasterization (raster.hip) -----------------------------------------------
 // One launch over the tiles of all views; view v's pixels go to
 // out + (sum of earlier views' pixels) * channels, likewise n_blend.
+// state / last (optional): final T, T_x, T_y, T_xy per pixel and the end of
+// its walked list, for the backward pass.
 hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
                          const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,
                          const gs_raster_cfg& cfg, bool grads, float* out, int32_t* n_blend,
-                         hipStream_t stream);
+                         float* state, int32_t* last, hipStream_t stream);
+// dsplat [n_records, 9] (zeroed here): mean x, mean y, conic a, b, c, opacity, rgb.
+hipError_t launch_raster_backward(const gs_splat* splats, const int32_t* sorted_ids,
+                                  const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,
+                                  const gs_raster_cfg& cfg, const float* state, const int32_t* last,
+                                  const float* dout, int64_t n_records, float* dsplat,
+                                  hipStream_t stream);
 
 // ---- upscaling (upscale.hip) ---------------------------------------------------
 // Views are concatenated in both buffers; sizes are host arrays [nv][2].
 hipError_t launch_upscale(const float* in, int32_t nv, const int32_t* lo_sizes, float* out,
                           const int32_t* hi_sizes, int32_t band_rows, hipStream_t stream);
+hipError_t launch_upscale_backward(const float* d_out, int32_t nv, const int32_t* lo_sizes,
+                                   float* d_in, const int32_t* hi_sizes, hipStream_t stream);
 hipError_t launch_fd_slopes(const float* img, int32_t w, int32_t h, float* out,
                             hipStream_t stream);
 

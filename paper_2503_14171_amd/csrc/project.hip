@@ -237,12 +237,255 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
   rect_out[o] = rect;
 }
 
-}  // namespace
+// Gradient of the SH colour sum_k Y_k(d) coef_k with respect to the unit
+// direction d: derivatives of the basis polynomials above.
+template <int DEG>
+__device__ __forceinline__ void sh_grad(double x, double y, double z, const double* w, double& gx,
+                                        double& gy, double& gz) {
+  // w[k] = sum_ch g_ch coef_k[ch] (the colour adjoint folded in)
+  const double K1 = 0.4886025119029199;
+  const double K2a = 1.0925484305920792, K2b = 0.31539156525252005, K2c = 0.5462742152960396;
+  const double K3a = 0.5900435899266435, K3b = 2.890611442640554, K3c = 0.4570457994644658,
+               K3d = 0.3731763325901154, K3e = 1.445305721320277;
+  gx = gy = gz = 0.0;
+  if (DEG < 1) return;
+  gy += -K1 * w[1];
+  gz += K1 * w[2];
+  gx += -K1 * w[3];
+  if (DEG < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  gx += K2a * y * w[4];
+  gy += K2a * x * w[4];
+  gy += -K2a * z * w[5];
+  gz += -K2a * y * w[5];
+  gx += -2.0 * K2b * x * w[6];
+  gy += -2.0 * K2b * y * w[6];
+  gz += 4.0 * K2b * z * w[6];
+  gx += -K2a * z * w[7];
+  gz += -K2a * x * w[7];
+  gx += 2.0 * K2c * x * w[8];
+  gy += -2.0 * K2c * y * w[8];
+  if (DEG < 3) return;
+  gx += -6.0 * K3a * x * y * w[9];
+  gy += -3.0 * K3a * (xx - yy) * w[9];
+  gx += K3b * y * z * w[10];
+  gy += K3b * x * z * w[10];
+  gz += K3b * x * y * w[10];
+  gx += 2.0 * K3c * x * y * w[11];
+  gy += -K3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
+  gz += -8.0 * K3c * y * z * w[11];
+  gx += -6.0 * K3d * x * z * w[12];
+  gy += -6.0 * K3d * y * z * w[12];
+  gz += K3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
+  gx += -K3c * (4.0 * zz - 3.0 * xx - yy) * w[13];
+  gy += 2.0 * K3c * x * y * w[13];
+  gz += -8.0 * K3c * x * z * w[13];
+  gx += 2.0 * K3e * x * z * w[14];
+  gy += -2.0 * K3e * y * z * w[14];
+  gz += K3e * (xx - yy) * w[14];
+  gx += -3.0 * K3a * (xx - yy) * w[15];
+  gy += 6.0 * K3a * x * y * w[15];
+}
 
-hipError_t launch_project(int64_t n, const float* means, const float* log_scales,
-                          const float* quats, const float* opacity, const float* sh, int32_t nv,
-                          const gs_camera* cams, const gs_raster_cfg& cfg, gs_splat* splats,
-                          float* depth, int32_t* rect, hipStream_t stream) {
+// Backward of the projection: dL/d(mean2d, conic, opacity, rgb) of every
+// (view, Gaussian) record -> dL/d(means, log_scales, quats, opacity, sh),
+// summed over the views.  One thread per Gaussian; the forward geometry is
+// recomputed in FP64 and the chain rule applied step by step:
+//   conic Q = Sigma'^-1:  dL/dSigma' = -Q (dL/dQ) Q  (dL/dQ symmetric, b counted twice)
+//   Sigma' = P S^2 P^T + dilation I, P = M R, M = J W:
+//     dL/dP = 2 dL/dSigma' P S^2, dL/ds_k^2 = (P^T dL/dSigma' P)_kk,
+//     dL/dR = M^T dL/dP, dL/dM = dL/dP R^T, dL/dJ = dL/dM W^T
+//   J(t) with the frustum-clamped direction, mean2d(t), t = W mu + t_W;
+//   R(q / |q|); colour max(0, sum Y_k(d) k + 1/2), d = (mu - cam) / |mu - cam|.
+template <int DEG>
+__global__ __launch_bounds__(256) void project_bwd_kernel(
+    ProjParams p, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ opacity,
+    const float* __restrict__ sh, const float* __restrict__ dsplat, float* __restrict__ d_means,
+    float* __restrict__ d_ls, float* __restrict__ d_quats, float* __restrict__ d_opacity,
+    float* __restrict__ d_sh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  const double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
+  const double ls[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
+  const float4 q4 = reinterpret_cast<const float4*>(quats)[i];
+  const double qv[4] = {q4.x, q4.y, q4.z, q4.w};
+  const double qn2 = qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3];
+  double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gsig = 0.0;
+  float gsh[3 * nb];  // FP32 accumulation over at most 16 views
+#pragma unroll
+  for (int k = 0; k < 3 * nb; ++k) gsh[k] = 0.f;
+  const double qi = qn2 > 0.0 ? 1.0 / sqrt(qn2) : 0.0;
+  const double w = qv[0] * qi, x = qv[1] * qi, y = qv[2] * qi, z = qv[3] * qi;
+  const double R[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                          {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                          {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+  const double s2[3] = {exp(2.0 * ls[0]), exp(2.0 * ls[1]), exp(2.0 * ls[2])};
+  double gR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+
+  for (int vi = 0; vi < p.nv; ++vi) {
+    const float* ds = dsplat + ((int64_t)vi * p.n + i) * 9;
+    const float g_mx = ds[0], g_my = ds[1], g_a = ds[2], g_b = ds[3], g_c = ds[4];
+    const float g_sig = ds[5], g_r = ds[6], g_g = ds[7], g_bl = ds[8];
+    if (g_mx == 0.f && g_my == 0.f && g_a == 0.f && g_b == 0.f && g_c == 0.f && g_sig == 0.f &&
+        g_r == 0.f && g_g == 0.f && g_bl == 0.f)
+      continue;  // never rasterized in this view (culled records have no gradient)
+    const ProjView& cv = p.view[vi];
+    const double* V = cv.V;
+    const double t0 = ((V[0] * mu[0] + V[1] * mu[1]) + V[2] * mu[2]) + V[3];
+    const double t1 = ((V[4] * mu[0] + V[5] * mu[1]) + V[6] * mu[2]) + V[7];
+    const double t2 = ((V[8] * mu[0] + V[9] * mu[1]) + V[10] * mu[2]) + V[11];
+    const double itz = 1.0 / t2;
+    const double rx0 = t0 * itz, ry0 = t1 * itz;
+    const double rx = fmin(cv.limx, fmax(-cv.limx, rx0));
+    const double ry = fmin(cv.limy, fmax(-cv.limy, ry0));
+    const bool clx = rx != rx0, cly = ry != ry0;
+    const double j00 = cv.fx * itz, j02 = -cv.fx * rx * itz;
+    const double j11 = cv.fy * itz, j12 = -cv.fy * ry * itz;
+    double M[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      M[0][c] = j00 * V[c] + j02 * V[8 + c];
+      M[1][c] = j11 * V[4 + c] + j12 * V[8 + c];
+    }
+    double P[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P[r][c] = M[r][0] * R[0][c] + M[r][1] * R[1][c] + M[r][2] * R[2][c];
+    double sxx = p.dilation, sxy = 0.0, syy = p.dilation;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      sxx += P[0][k] * P[0][k] * s2[k];
+      sxy += P[0][k] * P[1][k] * s2[k];
+      syy += P[1][k] * P[1][k] * s2[k];
+    }
+    const double det = sxx * syy - sxy * sxy;
+    const double id = 1.0 / det;
+    const double Qa = syy * id, Qb = -sxy * id, Qc = sxx * id;
+    // dL/dSigma' = -Q G Q with G = [[g_a, g_b/2], [g_b/2, g_c]]
+    const double G00 = g_a, G01 = 0.5 * g_b, G11 = g_c;
+    const double QG00 = Qa * G00 + Qb * G01, QG01 = Qa * G01 + Qb * G11;
+    const double QG10 = Qb * G00 + Qc * G01, QG11 = Qb * G01 + Qc * G11;
+    const double D00 = -(QG00 * Qa + QG01 * Qb), D01 = -(QG00 * Qb + QG01 * Qc);
+    const double D11 = -(QG10 * Qb + QG11 * Qc);
+    double gP[2][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gP[0][k] = 2.0 * (D00 * P[0][k] + D01 * P[1][k]) * s2[k];
+      gP[1][k] = 2.0 * (D01 * P[0][k] + D11 * P[1][k]) * s2[k];
+      const double gs2 = P[0][k] * (D00 * P[0][k] + D01 * P[1][k]) +
+                         P[1][k] * (D01 * P[0][k] + D11 * P[1][k]);
+      gls[k] += gs2 * 2.0 * s2[k];
+    }
+    // dL/dR = M^T gP, dL/dM = gP R^T
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gR[r][c] += M[0][r] * gP[0][c] + M[1][r] * gP[1][c];
+    double gM[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gM[r][c] = gP[r][0] * R[c][0] + gP[r][1] * R[c][1] + gP[r][2] * R[c][2];
+    // dL/dJ for the four non-zero entries (M_r. = sum_c J_rc W_c.)
+    const double gJ00 = gM[0][0] * V[0] + gM[0][1] * V[1] + gM[0][2] * V[2];
+    const double gJ02 = gM[0][0] * V[8] + gM[0][1] * V[9] + gM[0][2] * V[10];
+    const double gJ11 = gM[1][0] * V[4] + gM[1][1] * V[5] + gM[1][2] * V[6];
+    const double gJ12 = gM[1][0] * V[8] + gM[1][1] * V[9] + gM[1][2] * V[10];
+    const double itz2 = itz * itz;
+    double gt0 = 0.0, gt1 = 0.0, gt2 = 0.0;
+    gt2 += -cv.fx * itz2 * gJ00 - cv.fy * itz2 * gJ11;
+    // j02 = -fx rx / t2 with rx = t0 / t2 unless clamped
+    if (clx) {
+      gt2 += cv.fx * rx * itz2 * gJ02;
+    } else {
+      gt0 += -cv.fx * itz2 * gJ02;
+      gt2 += 2.0 * cv.fx * t0 * itz2 * itz * gJ02;
+    }
+    if (cly) {
+      gt2 += cv.fy * ry * itz2 * gJ12;
+    } else {
+      gt1 += -cv.fy * itz2 * gJ12;
+      gt2 += 2.0 * cv.fy * t1 * itz2 * itz * gJ12;
+    }
+    // mean2d = (fx t0 / t2 + cx, fy t1 / t2 + cy)
+    gt0 += cv.fx * itz * g_mx;
+    gt1 += cv.fy * itz * g_my;
+    gt2 += -(cv.fx * t0 * g_mx + cv.fy * t1 * g_my) * itz2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gmu[c] += V[c] * gt0 + V[4 + c] * gt1 + V[8 + c] * gt2;
+    gsig += g_sig;
+    // colour: max(0, s + 1/2) per channel, s = sum_k Y_k(d) coef_k
+    double dx = mu[0] - cv.cam[0], dy = mu[1] - cv.cam[1], dz = mu[2] - cv.cam[2];
+    const double dn2 = dx * dx + dy * dy + dz * dz;
+    const double idn = dn2 > 0.0 ? 1.0 / sqrt(dn2) : 0.0;
+    if (dn2 > 0.0) {
+      dx *= idn;
+      dy *= idn;
+      dz *= idn;
+    } else {
+      dx = 0.0;
+      dy = 0.0;
+      dz = 1.0;
+    }
+    float Y[nb];
+    sh_eval<DEG>((float)dx, (float)dy, (float)dz, Y);
+    const float* shg = sh + (int64_t)3 * nb * i;
+    float gch[3] = {g_r, g_g, g_bl};
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float col = 0.f;
+#pragma unroll
+      for (int k = 0; k < nb; ++k) col = fmaf(Y[k], shg[3 * k + ch], col);
+      if (!(col + 0.5f > 0.f)) gch[ch] = 0.f;  // clamped at zero
+    }
+    double wk[nb];
+#pragma unroll
+    for (int k = 0; k < nb; ++k) {
+      wk[k] = (double)gch[0] * shg[3 * k] + (double)gch[1] * shg[3 * k + 1] +
+              (double)gch[2] * shg[3 * k + 2];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) gsh[3 * k + ch] = fmaf(Y[k], gch[ch], gsh[3 * k + ch]);
+    }
+    if (dn2 > 0.0) {
+      double gdx, gdy, gdz;
+      sh_grad<DEG>(dx, dy, dz, wk, gdx, gdy, gdz);
+      // d = v / |v|: dL/dv = (g - d (d . g)) / |v|
+      const double dg = dx * gdx + dy * gdy + dz * gdz;
+      gmu[0] += (gdx - dx * dg) * idn;
+      gmu[1] += (gdy - dy * dg) * idn;
+      gmu[2] += (gdz - dz * dg) * idn;
+    }
+  }
+  // quaternion: dL/dq-hat from dL/dR, then the normalisation
+  double gqh[4];
+  gqh[0] = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+  gqh[1] = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] +
+                  z * gR[2][0] + w * gR[2][1] - 2.0 * x * gR[2][2]);
+  gqh[2] = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
+                  w * gR[2][0] + z * gR[2][1] - 2.0 * y * gR[2][2]);
+  gqh[3] = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] -
+                  2.0 * z * gR[1][1] + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+  const double qh[4] = {w, x, y, z};
+  const double dq = qh[0] * gqh[0] + qh[1] * gqh[1] + qh[2] * gqh[2] + qh[3] * gqh[3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gq[k] = (gqh[k] - qh[k] * dq) * qi;
+  for (int c = 0; c < 3; ++c) {
+    d_means[3 * i + c] = (float)gmu[c];
+    d_ls[3 * i + c] = (float)gls[c];
+  }
+  reinterpret_cast<float4*>(d_quats)[i] =
+      make_float4((float)gq[0], (float)gq[1], (float)gq[2], (float)gq[3]);
+  d_opacity[i] = (float)gsig;
+  float* gs = d_sh + (int64_t)3 * nb * i;
+#pragma unroll
+  for (int k = 0; k < 3 * nb; ++k) gs[k] = gsh[k];
+}
+
+ProjParams make_proj_params(int64_t n, int32_t nv, const gs_camera* cams,
+                            const gs_raster_cfg& cfg) {
   ProjParams p{};
   p.n = n;
   p.nv = nv;
@@ -265,6 +508,16 @@ hipError_t launch_project(int64_t n, const float* means, const float* log_scales
     c.limx = kFrustumClamp * (0.5 * cam.width) / (double)cam.fx;
     c.limy = kFrustumClamp * (0.5 * cam.height) / (double)cam.fy;
   }
+  return p;
+}
+
+}  // namespace
+
+hipError_t launch_project(int64_t n, const float* means, const float* log_scales,
+                          const float* quats, const float* opacity, const float* sh, int32_t nv,
+                          const gs_camera* cams, const gs_raster_cfg& cfg, gs_splat* splats,
+                          float* depth, int32_t* rect, hipStream_t stream) {
+  const ProjParams p = make_proj_params(n, nv, cams, cfg);
   const int threads = 256;
   const int64_t chunks = ceil_div(n, threads);
   const int64_t blocks = nv > 1 ? xcd_grid(chunks * nv) : chunks;
@@ -275,6 +528,23 @@ hipError_t launch_project(int64_t n, const float* means, const float* log_scales
     case 1: project_kernel<1><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
     case 2: project_kernel<2><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
     default: project_kernel<3><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_backward(int64_t n, const float* means, const float* log_scales,
+                                   const float* quats, const float* opacity, const float* sh,
+                                   int32_t nv, const gs_camera* cams, const gs_raster_cfg& cfg,
+                                   const float* dsplat, float* d_means, float* d_log_scales,
+                                   float* d_quats, float* d_opacity, float* d_sh,
+                                   hipStream_t stream) {
+  const ProjParams p = make_proj_params(n, nv, cams, cfg);
+  const dim3 g((unsigned)ceil_div(n, 256)), b(256);
+  switch (cfg.sh_degree) {
+    case 0: project_bwd_kernel<0><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, dsplat, d_means, d_log_scales, d_quats, d_opacity, d_sh); break;
+    case 1: project_bwd_kernel<1><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, dsplat, d_means, d_log_scales, d_quats, d_opacity, d_sh); break;
+    case 2: project_bwd_kernel<2><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, dsplat, d_means, d_log_scales, d_quats, d_opacity, d_sh); break;
+    default: project_bwd_kernel<3><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, dsplat, d_means, d_log_scales, d_quats, d_opacity, d_sh); break;
   }
   return hipGetLastError();
 }
