@@ -49,18 +49,18 @@ def tune(renderer, cams, hi_sizes, cfg: dict, tiles=(8, 16, 32), batch_divs=(1, 
     for tile in tiles:
         for div in batch_divs:
             c = dict(cfg, tile_size=tile, batch=tile * tile // div)
-            vb = ViewBatch(renderer, cams, hi_sizes, c, band_rows=16, capacity=capacity, direct=direct)
+            vb = ViewBatch(renderer, cams, hi_sizes, c, band_rows=8, capacity=capacity, direct=direct)
             ms = _time(vb, reps)
-            trials.append(dict(tile_size=tile, batch=c["batch"], band_rows=16, ms=ms))
+            trials.append(dict(tile_size=tile, batch=c["batch"], band_rows=8, ms=ms))
             if log:
                 log(trials[-1])
             if best is None or ms < best[0]:
                 best = (ms, c)
             del vb
     ms0, c = best
-    rows_best = (ms0, 16)
+    rows_best = (ms0, 8)
     for rows in () if direct else band_rows:
-        if rows == 16:
+        if rows == 8:
             continue
         vb = ViewBatch(renderer, cams, hi_sizes, c, band_rows=rows)
         ms = _time(vb, reps)

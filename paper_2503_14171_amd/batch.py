@@ -20,7 +20,7 @@ class ViewBatch:
     """``direct=True`` is the baseline: the views rendered directly at their
     high-res sizes (plain compositing, no upscaling) into ``up``."""
 
-    def __init__(self, renderer, cams, hi_sizes, cfg: dict, band_rows: int = 16,
+    def __init__(self, renderer, cams, hi_sizes, cfg: dict, band_rows: int = 0,
                  capacity: int | None = None, direct: bool = False):
         if not 1 <= len(cams) <= 16 or len(cams) != len(hi_sizes):
             raise ValueError("need 1..16 cameras and one high-res size per camera")

@@ -29,7 +29,10 @@ namespace gsup {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
+#ifndef GSUP_SORT_ITEMS
+#define GSUP_SORT_ITEMS 16
+#endif
+constexpr int kItems = GSUP_SORT_ITEMS;  // elements per thread of a sort / scan block
 constexpr int kTile = kThreads * kItems;  // elements per sort / scan block
 constexpr int kWaves = kThreads / 64;
 

@@ -247,7 +247,7 @@ UpParams make_up_params(int32_t nv, const int32_t* lo_sizes, const int32_t* hi_s
 
 hipError_t launch_upscale(const float* in, int32_t nv, const int32_t* lo_sizes, float* out,
                           const int32_t* hi_sizes, int32_t band_rows, hipStream_t stream) {
-  if (band_rows <= 0) band_rows = 16;
+  if (band_rows <= 0) band_rows = 8;
   const UpParams p = make_up_params(nv, lo_sizes, hi_sizes, band_rows, nullptr);
   const int64_t blocks = p.blocks;
   const unsigned grid = (unsigned)xcd_grid(blocks);
