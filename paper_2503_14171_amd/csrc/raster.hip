@@ -296,12 +296,40 @@ RasterParams make_params(int32_t nv, const gs_camera* cams, const gs_raster_cfg&
 // adjoints go to the splat's mean, conic and opacity through
 // a = sigma exp(-q/2), a_x = -a u, a_y = -a v, a_xy = a (u v - b).
 // Every wave reduces a splat's contributions over its 64 pixels and adds them
-// to the splat's gradient record with one atomic per field.
+// to the splat's gradient record with one atomic per field (nine lanes, one
+// instruction).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum(float v) {
+// Sums nine per-lane values over the wave with a transposing butterfly: at
+// each of the first four steps a lane keeps half of its (padded to 16)
+// partial sums, sends the other half to its partner and adds what it
+// receives (8 + 4 + 2 + 1 exchanges instead of 9 x 6); two more steps finish
+// the sums.  Afterwards lane L with L % 4 == 0 holds the total of component
+// comp = 8 b5 + 4 b4 + 2 b3 + b2 (b_k the bits of L).
+template <int N>
+__device__ __forceinline__ void half_exchange(float (&v)[16], int lane, int bit) {
+  const bool hi = (lane >> bit) & 1;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+  for (int i = 0; i < N; ++i) {
+    const float send = hi ? v[i] : v[i + N];
+    const float keep = hi ? v[i + N] : v[i];
+    v[i] = keep + __shfl_xor(send, 1 << bit, 64);
+  }
+}
+
+__device__ __forceinline__ float wave_reduce9(const float (&g)[9], int lane, int& comp) {
+  float v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = i < 9 ? g[i] : 0.f;
+  half_exchange<8>(v, lane, 5);
+  half_exchange<4>(v, lane, 4);
+  half_exchange<2>(v, lane, 3);
+  half_exchange<1>(v, lane, 2);
+  float r = v[0];
+  r += __shfl_xor(r, 2, 64);
+  r += __shfl_xor(r, 1, 64);
+  comp = (((lane >> 5) & 1) << 3) | (((lane >> 4) & 1) << 2) | (((lane >> 3) & 1) << 1) |
+         ((lane >> 2) & 1);
+  return r;
 }
 
 template <int TILE, int BATCH>
@@ -479,13 +507,9 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
         }
       }
       if (__ballot(act) != 0) {
-#pragma unroll
-        for (int f = 0; f < 9; ++f) g[f] = wave_sum(g[f]);
-        if (lane == 0) {
-          float* d = dsplat + (int64_t)s_id[j] * 9;
-#pragma unroll
-          for (int f = 0; f < 9; ++f) atomicAdd(d + f, g[f]);
-        }
+        int comp;
+        const float r = wave_reduce9(g, lane, comp);
+        if ((lane & 3) == 0 && comp < 9) atomicAdd(dsplat + (int64_t)s_id[j] * 9 + comp, r);
       }
     }
   }
