@@ -135,6 +135,16 @@ def run_gpu(args):
     assert rd.pairs_fit(cam, cfg), "pair count changed during the timed frames"
     stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])
     st_ms = stage.mean(0)
+    # the upscaler's own launch duration: back-to-back launches over the
+    # rotating buffer sets between two events on the launch stream
+    ue = _events(torch, 2)
+    nup = 4 * nsets
+    ue[0].record()
+    for k in range(nup):
+        rd.upscale(lows[k % nsets], W, H, ups[k % nsets])
+    ue[1].record()
+    torch.cuda.synchronize()
+    up_launch_ms = ue[0].elapsed_time(ue[1]) / nup
 
     # direct full-resolution render (plain compositing) on the same GPU, with
     # the frame's own tile size and with the other tile sizes; the best one
@@ -175,7 +185,7 @@ def run_gpu(args):
         return ms, st
 
     direct_all = {}
-    for tile in sorted({args.tile, 16, 32}):
+    for tile in sorted({args.tile, 16, 32, 64}):
         direct_all[tile] = time_direct(tile)
     best_tile = min(direct_all, key=lambda t: direct_all[t][0])
     ms_direct, dstage = direct_all[args.tile]
@@ -230,16 +240,6 @@ def run_gpu(args):
     achieved = frags * FLOP_PER_BLEND[True] / (ras_ms * 1e-3) / 1e12
     up_bytes = w * h * UPSCALE_BYTES_LO + W * H * UPSCALE_BYTES_HI
     up_gbs = up_bytes / (st_ms[3] * 1e-3) / 1e9
-    # the upscaler's own launch duration: back-to-back launches over the
-    # rotating buffer sets between two events on the launch stream
-    ue = _events(torch, 2)
-    nup = 4 * nsets
-    ue[0].record()
-    for k in range(nup):
-        rd.upscale(lows[k % nsets], W, H, ups[k % nsets])
-    ue[1].record()
-    torch.cuda.synchronize()
-    up_launch_ms = ue[0].elapsed_time(ue[1]) / nup
     up_gbs_launch = up_bytes / (up_launch_ms * 1e-3) / 1e9
     value = W * H / (ms_step * 1e-3) / 1e6
     direct_value = W * H / (ms_direct * 1e-3) / 1e6
@@ -275,7 +275,7 @@ def run_batch(args):
     rd = Renderer(sc)
     t0 = time.perf_counter()
     tuned = autotune.tune(rd, cams, hi, cfg0, reps=5)
-    tuned_d = autotune.tune(rd, cams, hi, cfg0, reps=3, direct=True, tiles=(16, 32), batch_divs=(1, 2))
+    tuned_d = autotune.tune(rd, cams, hi, cfg0, reps=3, direct=True, tiles=(16, 32, 64), batch_divs=(1, 2))
     tune_s = time.perf_counter() - t0
     cfg = dict(cfg0, tile_size=tuned["tile_size"], batch=tuned["batch"])
     cfg_d = dict(cfg0, tile_size=tuned_d["tile_size"], batch=tuned_d["batch"])
@@ -524,7 +524,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scene_x4", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle compositing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -572,7 +572,7 @@ def main():
         "roofline": {"kernel": "gs_raster_grad", "bound": "alu",
                      "achieved": round(res["achieved_tflops"], 3), "peak": FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(res["achieved_tflops"] / FP32_VALU_TFLOPS, 4),
-                     "traffic": measured_traffic("gs_raster_grad") if (args.workload, args.tile) == ("scene_x4", 16) else None,
+                     "traffic": measured_traffic("gs_raster_grad") if (args.workload, args.tile) == ("scene_x4", 32) else None,
                      "units": f"{res['frags']} blended fragments x {FLOP_PER_BLEND[True]} FLOP"},
         "upscaler_roofline": {"kernel": "gs_upscale_hermite", "bound": "hbm",
                               "achieved": round(res["up_gbs_launch"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

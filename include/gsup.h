@@ -69,7 +69,8 @@ typedef struct gs_camera {
 
 /* Render settings.  The paper fixes none of these numbers; see each field. */
 typedef struct gs_raster_cfg {
-  int32_t tile_size; /* square screen tile edge in pixels: 8, 16 or 32 */
+  int32_t tile_size; /* square screen tile of the per-tile lists, in pixels: 8, 16, 32 or 64
+                        (32x32 and 64x64 lists are rasterized by 16x16 workgroups) */
   int32_t sh_degree; /* degree of the SH colour, 0..3 */
   float dilation;    /* px^2 added to the 2D covariance diagonal (low-pass), >= 0; 3DGS uses 0.3 */
   float alpha_min;   /* fragments with alpha < alpha_min are skipped, in (0, alpha_max) */
@@ -77,7 +78,9 @@ typedef struct gs_raster_cfg {
   float t_min;       /* a pixel stops once its transmittance after a blend is < t_min, in (0, 1) */
   float bg[3];       /* background colour behind the last fragment */
   int32_t batch;     /* splats staged per LDS batch in the rasterizer: 0 or tile_size^2 (one per
-                        thread), tile_size^2 / 2 or tile_size^2 / 4; changes only the speed */
+                        thread), tile_size^2 / 2 or tile_size^2 / 4 (for tile_size 32 and 64
+                        these are per list tile, split over its 16x16 workgroups); changes only the
+                        speed */
 } gs_raster_cfg;
 
 /* A projected Gaussian (48 bytes, 16-byte aligned).  The 2D mean is kept in

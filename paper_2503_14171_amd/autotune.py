@@ -2,7 +2,7 @@
 
 For one scene size and one set of views it times, on the GPU, the captured
 graph of :class:`~paper_2503_14171_amd.batch.ViewBatch` for every tile size
-(8, 16, 32) and LDS batch (tile^2, tile^2/2, tile^2/4), then the upscale band
+(8, 16, 32, 64) and LDS batch (tile^2, tile^2/2, tile^2/4), then the upscale band
 height (4, 8, 16, 32 output rows per workgroup) for the best of those, and
 keeps the fastest setting.  None of the settings changes the images (the
 tile size only through the FP32 rounding of tile-relative offsets); they
@@ -34,7 +34,7 @@ def _time(vb: ViewBatch, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def tune(renderer, cams, hi_sizes, cfg: dict, tiles=(8, 16, 32), batch_divs=(1, 2, 4),
+def tune(renderer, cams, hi_sizes, cfg: dict, tiles=(8, 16, 32, 64), batch_divs=(1, 2, 4),
          band_rows=(4, 8, 16, 32), reps: int = 10, log=None, direct: bool = False) -> dict:
     """Fastest (tile_size, batch, band_rows) for these views; returns a dict
     with the setting, its ms per frame and every trial.  ``direct`` tunes the

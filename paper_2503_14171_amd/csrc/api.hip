@@ -45,8 +45,9 @@ gs_status check_camera(const char* fn, const gs_camera* cam) {
 
 gs_status check_cfg(const char* fn, const gs_raster_cfg* cfg) {
   if (!cfg) return fail(GS_ERR_INVALID_ARGUMENT, "%s: cfg is NULL", fn);
-  if (cfg->tile_size != 8 && cfg->tile_size != 16 && cfg->tile_size != 32)
-    return fail(GS_ERR_UNSUPPORTED, "%s: tile_size %d (supported: 8, 16, 32)", fn, cfg->tile_size);
+  if (cfg->tile_size != 8 && cfg->tile_size != 16 && cfg->tile_size != 32 && cfg->tile_size != 64)
+    return fail(GS_ERR_UNSUPPORTED, "%s: tile_size %d (supported: 8, 16, 32, 64)", fn,
+                cfg->tile_size);
   if (cfg->sh_degree < 0 || cfg->sh_degree > 3)
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: sh_degree %d outside [0, 3]", fn, cfg->sh_degree);
   if (!(cfg->dilation >= 0.f) || !finite(cfg->dilation))
@@ -144,7 +145,8 @@ gs_status project_impl(const char* fn, int64_t n, const float* means, const floa
 size_t bin_sort_ws(int64_t n, int32_t nv, const gs_camera* cams, const gs_raster_cfg* cfg,
                    int64_t capacity) {
   if (!cams || !cfg || nv < 1 || nv > GS_MAX_VIEWS || n < 0 || capacity < 0 ||
-      (cfg->tile_size != 8 && cfg->tile_size != 16 && cfg->tile_size != 32))
+      (cfg->tile_size != 8 && cfg->tile_size != 16 && cfg->tile_size != 32 &&
+       cfg->tile_size != 64))
     return 0;
   for (int v = 0; v < nv; ++v)
     if (cams[v].width < 1 || cams[v].height < 1) return 0;

@@ -16,9 +16,10 @@
 // with alpha_x = -alpha u, alpha_y = -alpha v, alpha_xy = alpha (u v - b),
 // (u, v) = Q d, d = pixel - mean, Q = [[a, b], [b, c]] the conic.
 //
-// Work decomposition (gfx950): one workgroup per screen tile (8x8, 16x16 or
-// 32x32 pixels), one pixel per lane, and every wave64 owns one 8x8 quadrant
-// of the tile.  The tile's splats stream through LDS in batches of up to one
+// Work decomposition (gfx950): one workgroup per screen tile of 8x8 or 16x16
+// pixels (a 32x32 or 64x64 list tile is rasterized by four or sixteen 16x16
+// workgroups that share its list), one pixel per lane, and every wave64 owns one 8x8
+// quadrant of the tile.  The tile's splats stream through LDS in batches of up to one
 // splat per thread (BATCH = TILE^2, or TILE^2/2, TILE^2/4); while staging, each thread marks the quadrants its splat's
 // support box meets, and each wave then compacts the batch (ballot + prefix
 // popcount) into its own LDS list of hits in depth order, so a wave only
@@ -57,7 +58,7 @@ struct RasterParams {
 // (covers FP32 rounding of the box and of the per-pixel alpha test).
 constexpr float kCullMargin = 0.25f;
 
-template <int TILE, bool GRAD, int BATCH>
+template <int TILE, bool GRAD, int BATCH, int SUB>
 __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
                                                             const gs_splat* __restrict__ splats,
                                                             const int32_t* __restrict__ ids,
@@ -77,19 +78,23 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
   __shared__ uint32_t s_mask[NW > 1 ? BATCH : 1];                // quadrants a staged splat can reach
   __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];  // per-wave hits, batch order
 
-  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+  // a workgroup covers one TILE x TILE part of a (TILE SUB)^2 list tile
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t tile = blk / (SUB * SUB);
   if (tile >= p.tiles) return;
+  const int sub = (int)(blk % (SUB * SUB));
   int vi = 0;  // the view this tile belongs to (uniform over the block)
   while (vi + 1 < p.nv && (uint32_t)tile >= p.view[vi + 1].tile_off) ++vi;
   const int width = p.view[vi].width, height = p.view[vi].height, tiles_x = p.view[vi].tiles_x;
   const int64_t local = tile - p.view[vi].tile_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int tx = (int)(local % tiles_x), ty = (int)(local / tiles_x);
+  const int x0 = tx * TILE * SUB + (sub % SUB) * TILE, y0 = ty * TILE * SUB + (sub / SUB) * TILE;
   const int lx = (wave % QX) * 8 + (lane & 7), ly = (wave / QX) * 8 + (lane >> 3);
-  const int px = tx * TILE + lx, py = ty * TILE + ly;
+  const int px = x0 + lx, py = y0 + ly;
   const bool inside = px < width && py < height;
   const float fx = (float)lx, fy = (float)ly;
-  const double ox = (double)tx * TILE, oy = (double)ty * TILE;
+  const double ox = (double)x0, oy = (double)y0;
   const int2 rg = ranges[tile];
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
@@ -232,22 +237,24 @@ struct RasterOut {
   int32_t* last;
 };
 
-template <int TILE, bool GRAD, int BATCH>
+template <int TILE, bool GRAD, int BATCH, int SUB>
 void launch(const RasterParams& p, const gs_splat* splats, const int32_t* ids, const int2* ranges,
             const RasterOut& o, hipStream_t stream) {
-  const int64_t grid = xcd_grid(p.tiles);
-  raster_kernel<TILE, GRAD, BATCH><<<(unsigned)grid, TILE * TILE, 0, stream>>>(
+  const int64_t grid = xcd_grid(p.tiles * SUB * SUB);
+  raster_kernel<TILE, GRAD, BATCH, SUB><<<(unsigned)grid, TILE * TILE, 0, stream>>>(
       p, splats, ids, ranges, o.out, o.n_blend, o.state, o.last);
 }
 
-// batch: 0 or TILE^2 -> one splat per thread; TILE^2 / 2 and TILE^2 / 4 -> fewer
-template <int TILE, bool GRAD>
+// List tiles of edge TILE * SUB, workgroups of TILE x TILE pixels.  batch
+// (relative to the list tile, as in gs_raster_cfg): its area -> one splat per
+// thread; a half or a quarter of it -> that fraction of the threads stage.
+template <int TILE, bool GRAD, int SUB>
 void launch_batch(int batch, const RasterParams& p, const gs_splat* splats, const int32_t* ids,
                   const int2* ranges, const RasterOut& o, hipStream_t stream) {
-  constexpr int NT = TILE * TILE;
-  if (batch == NT / 4) launch<TILE, GRAD, NT / 4>(p, splats, ids, ranges, o, stream);
-  else if (batch == NT / 2) launch<TILE, GRAD, NT / 2>(p, splats, ids, ranges, o, stream);
-  else launch<TILE, GRAD, NT>(p, splats, ids, ranges, o, stream);
+  constexpr int NT = TILE * TILE, LT = NT * SUB * SUB;
+  if (batch == LT / 4) launch<TILE, GRAD, NT / 4, SUB>(p, splats, ids, ranges, o, stream);
+  else if (batch == LT / 2) launch<TILE, GRAD, NT / 2, SUB>(p, splats, ids, ranges, o, stream);
+  else launch<TILE, GRAD, NT, SUB>(p, splats, ids, ranges, o, stream);
 }
 
 RasterParams make_params(int32_t nv, const gs_camera* cams, const gs_raster_cfg& cfg) {
@@ -332,7 +339,7 @@ __device__ __forceinline__ float wave_reduce9(const float (&g)[9], int lane, int
   return r;
 }
 
-template <int TILE, int BATCH>
+template <int TILE, int BATCH, int SUB>
 __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
     RasterParams p, const gs_splat* __restrict__ splats, const int32_t* __restrict__ ids,
     const int2* __restrict__ ranges, const float4* __restrict__ state,
@@ -349,19 +356,23 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
   __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];
   __shared__ int s_end;
 
-  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+  // the same workgroup-to-pixel layout as the forward (identical FP32 offsets)
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t tile = blk / (SUB * SUB);
   if (tile >= p.tiles) return;
+  const int sub = (int)(blk % (SUB * SUB));
   int vi = 0;
   while (vi + 1 < p.nv && (uint32_t)tile >= p.view[vi + 1].tile_off) ++vi;
   const int width = p.view[vi].width, height = p.view[vi].height, tiles_x = p.view[vi].tiles_x;
   const int64_t local = tile - p.view[vi].tile_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int tx = (int)(local % tiles_x), ty = (int)(local / tiles_x);
+  const int x0 = tx * TILE * SUB + (sub % SUB) * TILE, y0 = ty * TILE * SUB + (sub / SUB) * TILE;
   const int lx = (wave % QX) * 8 + (lane & 7), ly = (wave / QX) * 8 + (lane >> 3);
-  const int px = tx * TILE + lx, py = ty * TILE + ly;
+  const int px = x0 + lx, py = y0 + ly;
   const bool inside = px < width && py < height;
   const float fx = (float)lx, fy = (float)ly;
-  const double ox = (double)tx * TILE, oy = (double)ty * TILE;
+  const double ox = (double)x0, oy = (double)y0;
   const int2 rg = ranges[tile];
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t pix = p.view[vi].pix_off + (int64_t)py * width + px;
@@ -515,18 +526,18 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
   }
 }
 
-template <int TILE>
+template <int TILE, int SUB>
 void launch_bwd(int batch, const RasterParams& p, const gs_splat* splats, const int32_t* ids,
                 const int2* ranges, const float4* state, const int32_t* last, const float* dout,
                 float* dsplat, hipStream_t stream) {
-  constexpr int NT = TILE * TILE;
-  const unsigned grid = (unsigned)xcd_grid(p.tiles);
-  if (batch == NT / 4)
-    raster_bwd_kernel<TILE, NT / 4><<<grid, NT, 0, stream>>>(p, splats, ids, ranges, state, last, dout, dsplat);
-  else if (batch == NT / 2)
-    raster_bwd_kernel<TILE, NT / 2><<<grid, NT, 0, stream>>>(p, splats, ids, ranges, state, last, dout, dsplat);
+  constexpr int NT = TILE * TILE, LT = NT * SUB * SUB;
+  const unsigned grid = (unsigned)xcd_grid(p.tiles * SUB * SUB);
+  if (batch == LT / 4)
+    raster_bwd_kernel<TILE, NT / 4, SUB><<<grid, NT, 0, stream>>>(p, splats, ids, ranges, state, last, dout, dsplat);
+  else if (batch == LT / 2)
+    raster_bwd_kernel<TILE, NT / 2, SUB><<<grid, NT, 0, stream>>>(p, splats, ids, ranges, state, last, dout, dsplat);
   else
-    raster_bwd_kernel<TILE, NT><<<grid, NT, 0, stream>>>(p, splats, ids, ranges, state, last, dout, dsplat);
+    raster_bwd_kernel<TILE, NT, SUB><<<grid, NT, 0, stream>>>(p, splats, ids, ranges, state, last, dout, dsplat);
 }
 
 __global__ void zero_f32_kernel(float* p, int64_t n) {
@@ -544,14 +555,19 @@ hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
   const RasterOut o{out, n_blend, reinterpret_cast<float4*>(state), last};
   const int2* r2 = reinterpret_cast<const int2*>(tile_ranges);
   if (cfg.tile_size == 8) {
-    if (grads) launch_batch<8, true>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
-    else launch_batch<8, false>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
+    if (grads) launch_batch<8, true, 1>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
+    else launch_batch<8, false, 1>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
   } else if (cfg.tile_size == 16) {
-    if (grads) launch_batch<16, true>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
-    else launch_batch<16, false>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
+    if (grads) launch_batch<16, true, 1>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
+    else launch_batch<16, false, 1>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
+  } else if (cfg.tile_size == 32) {
+    // 32x32 list tiles, rasterized by 16x16 workgroups (four per list tile)
+    if (grads) launch_batch<16, true, 2>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
+    else launch_batch<16, false, 2>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
   } else {
-    if (grads) launch_batch<32, true>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
-    else launch_batch<32, false>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
+    // 64x64 list tiles, sixteen 16x16 workgroups each
+    if (grads) launch_batch<16, true, 4>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
+    else launch_batch<16, false, 4>(cfg.batch, p, splats, sorted_ids, r2, o, stream);
   }
   return hipGetLastError();
 }
@@ -566,9 +582,10 @@ hipError_t launch_raster_backward(const gs_splat* splats, const int32_t* sorted_
   const RasterParams p = make_params(nv, cams, cfg);
   const int2* r2 = reinterpret_cast<const int2*>(tile_ranges);
   const float4* s4 = reinterpret_cast<const float4*>(state);
-  if (cfg.tile_size == 8) launch_bwd<8>(cfg.batch, p, splats, sorted_ids, r2, s4, last, dout, dsplat, stream);
-  else if (cfg.tile_size == 16) launch_bwd<16>(cfg.batch, p, splats, sorted_ids, r2, s4, last, dout, dsplat, stream);
-  else launch_bwd<32>(cfg.batch, p, splats, sorted_ids, r2, s4, last, dout, dsplat, stream);
+  if (cfg.tile_size == 8) launch_bwd<8, 1>(cfg.batch, p, splats, sorted_ids, r2, s4, last, dout, dsplat, stream);
+  else if (cfg.tile_size == 16) launch_bwd<16, 1>(cfg.batch, p, splats, sorted_ids, r2, s4, last, dout, dsplat, stream);
+  else if (cfg.tile_size == 32) launch_bwd<16, 2>(cfg.batch, p, splats, sorted_ids, r2, s4, last, dout, dsplat, stream);
+  else launch_bwd<16, 4>(cfg.batch, p, splats, sorted_ids, r2, s4, last, dout, dsplat, stream);
   return hipGetLastError();
 }
 

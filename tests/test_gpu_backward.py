@@ -78,7 +78,8 @@ def _raster_setup(torch, oracle, sc, cam, cfg):
     return pr, b, low, state, last
 
 
-@pytest.mark.parametrize("tile,bg", [(16, (0.0, 0.0, 0.0)), (8, (0.2, 0.5, 0.9)), (32, (0.0, 0.0, 0.0))])
+@pytest.mark.parametrize("tile,bg", [(16, (0.0, 0.0, 0.0)), (8, (0.2, 0.5, 0.9)), (32, (0.0, 0.0, 0.0)),
+                                     (64, (0.1, 0.1, 0.1))])
 def test_raster_backward_matches_oracle(torch_mod, oracle, tile, bg):
     torch = torch_mod
     from paper_2503_14171_amd import _lib as L

@@ -168,7 +168,7 @@ def test_tile_sizes_agree(torch_mod):
     cam = scenes.make_camera(960, 540)
     rd = Renderer(sc)
     outs = []
-    for tile in (8, 16, 32):
+    for tile in (8, 16, 32, 64):
         print(f"tile agreement tile={tile}", flush=True)
         outs.append(rd.render(cam, scenes.render_config(3, tile_size=tile)).cpu().numpy())
     for other in outs[1:]:

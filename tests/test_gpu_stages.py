@@ -102,7 +102,7 @@ def _run_bin_sort(gs, depth32, rect, cam, cfg, capacity=None):
     return ids.cpu().numpy()[:K], ranges.cpu().numpy()
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
 def test_bin_sort_matches_lexsort_oracle_scene(gs, oracle, tile):
     from paper_2503_14171_amd import scenes
     sc = scenes.make_scene("clusters", 60000, 23, 0)
@@ -205,7 +205,7 @@ def _raster_stage(gs, oracle, sc, cam, cfg, want_grads=True, sample=None, seed=0
     return g[idx], nb[idx], ref
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("tile", [8, 16, 32, 64])
 @pytest.mark.parametrize("want_grads", [True, False])
 def test_raster_stage_tiny(gs, oracle, tile, want_grads):
     from paper_2503_14171_amd import scenes
@@ -221,7 +221,7 @@ def test_raster_stage_tiny(gs, oracle, tile, want_grads):
     np.testing.assert_array_equal(nb[clean], ref["n_blend"][clean])
 
 
-@pytest.mark.parametrize("tile", [16, 32])
+@pytest.mark.parametrize("tile", [16, 32, 64])
 def test_raster_stage_ragged_bg_opaque(gs, oracle, tile):
     """Image size not a multiple of the tile, non-zero background, opaque
     splats (alpha clamp and early termination everywhere)."""
