@@ -132,7 +132,8 @@ size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* 
  * Sec. "Differentiable 3D Gaussian Splatting", restricted to each tile).
  *
  * Inputs (device): depth [n] and rect [n,4] from gs_project (depth must be
- * positive, or +inf, wherever rect is non-empty: its bits are the sort key).
+ * positive wherever rect is non-empty: its bits are the sort key; a splat
+ * with depth +inf reaches no tile and its rect is not read).
  * Outputs:
  *   sorted_ids [capacity] int32  (device) splat indices; tile t's list is
  *                               sorted_ids[tile_ranges[2t] .. tile_ranges[2t+1]),

@@ -146,6 +146,14 @@ constexpr int kRounds = kSeg / 64;     // 64-element rounds per wave
 #endif
 constexpr int kMaxDigitBits = GSUP_MAX_DIGIT_BITS;
 static_assert(kMaxDigitBits >= 1 && kMaxDigitBits <= 11, "digit width");
+// Widest digit of the pair (tile id) sort: up to 2^kMaxTileDigitBits list
+// tiles sort in a single pass, whose digit counts are then the tile ranges.
+#ifndef GSUP_MAX_TILE_DIGIT_BITS
+#define GSUP_MAX_TILE_DIGIT_BITS 9
+#endif
+constexpr int kMaxTileDigitBits = GSUP_MAX_TILE_DIGIT_BITS;
+constexpr int kMaxAnyDigitBits = kMaxDigitBits > kMaxTileDigitBits ? kMaxDigitBits : kMaxTileDigitBits;
+static_assert(kMaxTileDigitBits >= 1 && kMaxTileDigitBits <= 11, "tile digit width");
 
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -368,15 +376,15 @@ hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* k
   return hipGetLastError();
 }
 
-// One stable pass over `bits` (1..kMaxDigitBits) bits starting at `shift`.
+// One stable pass over `bits` (1..kMaxAnyDigitBits) bits starting at `shift`.
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       int64_t m, const uint64_t* m_dev, int shift, int bits, uint32_t* hist,
                       uint32_t* totals, hipStream_t stream) {
   switch (bits) {
 #define GS_RADIX_CASE(B)                                                                  \
   case B:                                                                                 \
-    if (B <= kMaxDigitBits)                                                               \
-      return radix_pass_bits<(B <= kMaxDigitBits ? B : 1)>(kin, vin, kout, vout, m, m_dev,  \
+    if (B <= kMaxAnyDigitBits)                                                            \
+      return radix_pass_bits<(B <= kMaxAnyDigitBits ? B : 1)>(kin, vin, kout, vout, m, m_dev, \
                                                            shift, hist, totals, stream);  \
     break;
     GS_RADIX_CASE(1)
@@ -396,10 +404,10 @@ hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
   return hipErrorInvalidValue;
 }
 
-// Splits `bits` key bits into the fewest passes of at most kMaxDigitBits,
+// Splits `bits` key bits into the fewest passes of at most max_bits,
 // as evenly as possible; returns the pass count and fills widths[].
-int radix_plan(int bits, int widths[8]) {
-  const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+int radix_plan(int bits, int widths[8], int max_bits = kMaxDigitBits) {
+  const int passes = (bits + max_bits - 1) / max_bits;
   for (int k = 0; k < passes; ++k) widths[k] = bits / passes + (k < bits % passes ? 1 : 0);
   return passes;
 }
@@ -424,9 +432,13 @@ __device__ __forceinline__ int view_of(const ViewTiles& vt, uint32_t e) {
 }
 
 // Rectangles in depth order (clipped to their view's tile grid) and, per
-// block of kEmit splats, the sum of their tile counts.
+// block of kEmit splats, the sum of their tile counts.  Splats with an
+// infinite depth (the projection's mark for "reaches no tile") sort last and
+// get an empty rectangle without the random read of theirs.
+constexpr uint32_t kInfBits = 0x7F800000u;
 __global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
                                                             const uint32_t* __restrict__ order,
+                                                            const uint32_t* __restrict__ skeys,
                                                             const int4* __restrict__ rect,
                                                             ViewTiles vt,
                                                             int4* __restrict__ srect,
@@ -435,9 +447,12 @@ __global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
   const int64_t p = (int64_t)blockIdx.x * kEmit + threadIdx.x;
   uint64_t c = 0;
   if (p < n) {
-    const uint32_t e = order[p];
-    const int v = view_of(vt, e);
-    const int4 r = clip_rect(rect[e], vt.tiles_x[v], vt.tiles_y[v]);
+    int4 r = make_int4(0, 0, 0, 0);
+    if (skeys[p] != kInfBits) {
+      const uint32_t e = order[p];
+      const int v = view_of(vt, e);
+      r = clip_rect(rect[e], vt.tiles_x[v], vt.tiles_y[v]);
+    }
     srect[p] = r;
     c = rect_tiles(r);
   }
@@ -532,6 +547,33 @@ __global__ __launch_bounds__(kThreads) void tile_range_kernel(int64_t K, const u
   }
 }
 
+// Tile ranges from per-tile pair counts (tiles <= 2^kMaxAnyDigitBits): an
+// exclusive scan in one workgroup; a tile without pairs gets [0, 0).
+__global__ __launch_bounds__(kThreads) void ranges_from_counts_kernel(
+    const uint32_t* __restrict__ counts, int64_t tiles, int32_t* __restrict__ ranges) {
+  constexpr int R = 1 << kMaxAnyDigitBits;
+  constexpr int DPT = R > kThreads ? R / kThreads : 1;
+  __shared__ uint32_t s_w[kWaves];
+  uint32_t v[DPT], sum = 0;
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int64_t t = (int64_t)threadIdx.x * DPT + k;
+    v[k] = t < tiles ? counts[t] : 0u;
+    sum += v[k];
+  }
+  uint32_t excl;
+  block_exclusive_scan<uint32_t>(sum, &excl, s_w);
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int64_t t = (int64_t)threadIdx.x * DPT + k;
+    if (t < tiles) {
+      ranges[2 * t] = v[k] ? (int32_t)excl : 0;
+      ranges[2 * t + 1] = v[k] ? (int32_t)(excl + v[k]) : 0;
+    }
+    excl += v[k];
+  }
+}
+
 inline unsigned grid1d(int64_t n, int threads) { return (unsigned)ceil_div(n, threads); }
 
 }  // namespace
@@ -580,8 +622,8 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles) {
   p.off_pval = take(c4);
   const int64_t max_blocks = std::max<int64_t>(ceil_div(n1, kTile),
                                                ceil_div(std::max<int64_t>(capacity, 1), kTile));
-  p.off_hist = take(sizeof(uint32_t) * (size_t)((int64_t(1) << kMaxDigitBits) * max_blocks));
-  p.off_totals = take(sizeof(uint32_t) * (size_t)(1 << kMaxDigitBits));
+  p.off_hist = take(sizeof(uint32_t) * (size_t)((int64_t(1) << kMaxAnyDigitBits) * max_blocks));
+  p.off_totals = take(sizeof(uint32_t) * (size_t)(1 << kMaxAnyDigitBits));
   p.off_total = take(sizeof(uint64_t));
   p.bytes = off;
   return p;
@@ -633,11 +675,12 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     cur ^= 1;
   }
   const uint32_t* order = u32(p.off_gval[cur]);
+  const uint32_t* skeys = u32(p.off_gkey[cur]);
 
   // 2. rectangles in depth order, pair offsets per block of splats, total K
   int4* srect = reinterpret_cast<int4*>(ws + p.off_srect);
   const int64_t nbe = ceil_div(n, kEmit);
-  gather_rect_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, r4, vt, srect, bsum);
+  gather_rect_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, skeys, r4, vt, srect, bsum);
   GS_TRY(hipGetLastError(), "gather_rect_kernel");
   scan_small_kernel<uint64_t><<<1, kSmallThreads, 0, stream>>>(bsum, nbe, total);
   GS_TRY(hipGetLastError(), "pair offset scan");
@@ -661,7 +704,7 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
   GS_TRY(hipGetLastError(), "fill_i32_kernel");
   if (m == 0) return GS_OK;
-  passes = radix_plan(p.tile_bits, widths);
+  passes = radix_plan(p.tile_bits, widths, kMaxTileDigitBits);
   // values end in sorted_ids after `passes` ping-pong steps
   uint32_t* vbuf[2];
   vbuf[0] = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(sorted_ids) : u32(p.off_pval);
@@ -681,9 +724,16 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     shift += widths[k];
     cur ^= 1;
   }
-  tile_range_kernel<<<(unsigned)ceil_div(m, kTile), kThreads, 0, stream>>>(m, m_dev, kbuf[cur],
-                                                                           tile_ranges);
-  GS_TRY(hipGetLastError(), "tile_range_kernel");
+  if (passes == 1) {
+    // one pass: the digit of every pair is its whole tile id, so the pass's
+    // digit counts are the list lengths and their running sum the starts
+    ranges_from_counts_kernel<<<1, kThreads, 0, stream>>>(totals, p.tiles, tile_ranges);
+    GS_TRY(hipGetLastError(), "ranges_from_counts_kernel");
+  } else {
+    tile_range_kernel<<<(unsigned)ceil_div(m, kTile), kThreads, 0, stream>>>(m, m_dev, kbuf[cur],
+                                                                             tile_ranges);
+    GS_TRY(hipGetLastError(), "tile_range_kernel");
+  }
 #undef GS_TRY
   return GS_OK;
 }
