@@ -130,6 +130,66 @@ def test_validation_rejects_bad_calls(L):
     assert "overlap" in lib.gs_last_error_message().decode()
 
 
+@pytestmark_validation
+def test_validation_rejects_bad_batched_and_backward_calls(L):
+    from paper_2503_14171_amd import scenes
+    lib = L.lib()
+    cams = L.cameras([scenes.make_camera(64, 48), scenes.make_camera(32, 40)])
+    cfg = L.raster_cfg(scenes.render_config(0))
+    R = ctypes.byref
+    F = ctypes.c_void_p(4096)  # never dereferenced: every call below fails validation
+    I32 = ctypes.c_int32
+    # view counts outside [1, GS_MAX_VIEWS] and a missing camera array
+    for nv in (0, 17):
+        assert lib.gs_project_views(10, F, F, F, F, F, nv, cams, R(cfg), F, F, F, None) == L.GS_ERR_INVALID_ARGUMENT
+        assert "n_views" in lib.gs_last_error_message().decode()
+    assert lib.gs_raster_grad_views(F, F, F, 2, None, R(cfg), 1, F, None, None) == L.GS_ERR_INVALID_ARGUMENT
+    # a bad camera among the views
+    bad = L.cameras([scenes.make_camera(64, 48), dict(scenes.make_camera(32, 40), width=0)])
+    assert lib.gs_project_views(10, F, F, F, F, F, 2, bad, R(cfg), F, F, F, None) == L.GS_ERR_INVALID_ARGUMENT
+    # unsupported LDS batch and tile size
+    bad_batch = L.raster_cfg(scenes.render_config(0, tile_size=16, batch=100))
+    assert lib.gs_raster_grad_views(F, F, F, 2, cams, R(bad_batch), 1, F, None, None) == L.GS_ERR_UNSUPPORTED
+    assert "batch" in lib.gs_last_error_message().decode()
+    bad_tile = L.raster_cfg(scenes.render_config(0, tile_size=128))
+    assert lib.gs_raster_grad_views(F, F, F, 2, cams, R(bad_tile), 1, F, None, None) == L.GS_ERR_UNSUPPORTED
+    # n * n_views beyond the int32 record index
+    assert lib.gs_project_views(1 << 30, F, F, F, F, F, 2, cams, R(cfg), F, F, F, None) == L.GS_ERR_INVALID_ARGUMENT
+    # the batched bin sort needs a device counter; workspace too small
+    ws = lib.gs_bin_sort_views_workspace_size(10, 2, cams, R(cfg), 100)
+    assert ws > 0
+    assert lib.gs_bin_sort_views(10, 2, cams, R(cfg), F, F, 100, F, F, None, F, ws, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_bin_sort_views(10, 2, cams, R(cfg), F, F, 100, F, F, F, F, ws - 1, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_bin_sort_async(10, F, F, R(L.camera(scenes.make_camera(64, 48))), R(cfg), 100, F, F, None, F,
+                                 ws, None) == L.GS_ERR_INVALID_ARGUMENT
+    # upscaler views: bad band height, a view smaller than 2x2, overlapping buffers
+    lo = (I32 * 4)(16, 8, 4, 4)
+    hi = (I32 * 4)(32, 16, 8, 8)
+    assert lib.gs_upscale_hermite_views(F, 2, lo, ctypes.c_void_p(1 << 24), hi, 12, None) == L.GS_ERR_UNSUPPORTED
+    lo_bad = (I32 * 4)(16, 8, 1, 4)
+    assert lib.gs_upscale_hermite_views(F, 2, lo_bad, ctypes.c_void_p(1 << 24), hi, 0, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_upscale_hermite_views(F, 2, lo, ctypes.c_void_p(4096 + 64), hi, 0, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert "overlap" in lib.gs_last_error_message().decode()
+    # backward entry points: missing buffers, misaligned state, bad sizes
+    assert lib.gs_raster_grad_views_train(F, F, F, 2, cams, R(cfg), F, None, F, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_raster_grad_views_train(F, F, F, 2, cams, R(cfg), F, ctypes.c_void_p(4100), F,
+                                          None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_raster_grad_backward_views(F, F, F, 2, cams, R(cfg), F, F, F, 10, None, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_raster_grad_backward_views(F, F, F, 2, cams, R(cfg), F, F, F, -1, F, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_project_backward_views(10, F, F, F, F, F, 2, cams, R(cfg), F, F, F, None, F, F,
+                                         None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_project_backward_views(10, F, F, F, F, F, 2, cams, R(cfg), F, F, F, ctypes.c_void_p(4104), F, F,
+                                         None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_project_backward_views(0, None, None, None, None, None, 2, cams, R(cfg), None, None, None, None,
+                                         None, None, None) == L.GS_OK
+    assert lib.gs_upscale_hermite_backward_views(F, 2, lo_bad, ctypes.c_void_p(1 << 24), hi, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_upscale_hermite_backward_views(F, 2, lo, ctypes.c_void_p(4096 + 32), hi, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert "overlap" in lib.gs_last_error_message().decode()
+    # sizes on the host
+    assert lib.gs_num_tiles_views(2, cams, 16) == 4 * 3 + 2 * 3
+    assert lib.gs_num_tiles_views(0, cams, 16) == 0
+
+
 def test_binding_fails_loudly_without_library(L, monkeypatch):
     import paper_2503_14171_amd._lib as mod
     monkeypatch.setattr(mod, "_lib", None)

@@ -215,3 +215,27 @@ def test_training_chain_matches_oracle_and_finite_differences(torch_mod, oracle)
         assert abs(got[idx] - fd) <= REL * max(abs(fd), 1e-12), (k, idx, got[idx], fd)
         checked += 1
     assert checked == 3
+
+
+def test_backward_of_unseen_scene_is_zero(torch_mod):
+    """Every Gaussian behind the cameras: no fragment, no gradient (and no
+    NaN from culled records)."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.train import TrainViews, UpscaledRender
+    sc = scenes.make_scene("clusters", 500, 64, 2)
+    sc["means"] = (sc["means"] * np.float32(0.2) + np.float32([0.0, 0.0, -6.0])).astype(np.float32)
+    cams = [scenes.make_camera(40, 30), scenes.make_camera(24, 24)]
+    hi = [(80, 60), (48, 48)]
+    cfg = scenes.render_config(2)
+    params = {k: _dev(sc[k]).requires_grad_(True) for k in ("means", "log_scales", "quats", "opacity", "sh")}
+    tv = TrainViews(500, cams, hi, cfg)
+    print("backward: unseen scene", flush=True)
+    up = UpscaledRender.apply(params["means"], params["log_scales"], params["quats"], params["opacity"],
+                              params["sh"], tv)
+    (up * up).sum().backward()
+    torch.cuda.synchronize()
+    assert int(tv.n_pairs.item()) == 0
+    for k, p in params.items():
+        g = p.grad.cpu().numpy()
+        assert np.isfinite(g).all() and (g == 0).all(), k

@@ -230,3 +230,36 @@ def test_autotuner_picks_a_valid_setting(torch_mod):
     assert best["band_rows"] in (4, 8, 16, 32)
     assert best["ms"] > 0 and len(best["trials"]) >= 9
     assert autotune.tune(rd, cams, hi, scenes.render_config(3), reps=3) is best  # cached
+
+
+def test_views_empty_scene_and_blind_view(torch_mod):
+    """No Gaussians at all, and a view that sees none of them: background
+    everywhere, no pairs, derivatives zero."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.batch import ViewBatch
+    from paper_2503_14171_amd.render import Renderer
+    bg = (0.25, 0.5, 0.75)
+    cfg = scenes.render_config(3, bg=bg)
+    cams, hi = _rig(3)
+    empty = scenes.make_scene("scene", 0, 47, 3)
+    print("views: empty scene", flush=True)
+    vb = ViewBatch(Renderer(empty), cams, hi, cfg)
+    lows, ups = vb.render()
+    torch.cuda.synchronize()
+    assert int(vb.n_pairs.item()) == 0
+    for low, up in zip(lows, ups):
+        lo = low.cpu().numpy()
+        np.testing.assert_array_equal(lo[..., :3], np.broadcast_to(np.float32(bg), lo[..., :3].shape))
+        np.testing.assert_array_equal(lo[..., 3:], 0.0)
+        np.testing.assert_allclose(up.cpu().numpy(), np.broadcast_to(np.float32(bg), up.shape), atol=1e-6)
+    # a camera looking away from the scene next to one that sees it
+    sc = scenes.make_scene("scene", 20000, 48, 3)
+    away = scenes.make_camera(64, 48, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, -9.0))
+    sc["means"] = (sc["means"] * np.float32(0.3)).astype(np.float32)  # keep the shell out of view
+    vb = ViewBatch(Renderer(sc), [away, cams[0]], [(128, 96), hi[0]], cfg)
+    lows, ups = vb.render()
+    torch.cuda.synchronize()
+    lo = lows[0].cpu().numpy()
+    np.testing.assert_array_equal(lo[..., :3], np.broadcast_to(np.float32(bg), lo[..., :3].shape))
+    assert np.abs(lows[1].cpu().numpy()[..., :3] - np.float32(bg)).max() > 0.05
