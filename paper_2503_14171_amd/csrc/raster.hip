@@ -308,10 +308,25 @@ RasterParams make_params(int32_t nv, const gs_camera* cams, const gs_raster_cfg&
 // ---------------------------------------------------------------------------
 // Sums nine per-lane values over the wave with a transposing butterfly: at
 // each of the first four steps a lane keeps half of its (padded to 16)
-// partial sums, sends the other half to its partner and adds what it
+// partial sums, hands the other half to its partner and adds what it
 // receives (8 + 4 + 2 + 1 exchanges instead of 9 x 6); two more steps finish
 // the sums.  Afterwards lane L with L % 4 == 0 holds the total of component
-// comp = 8 b5 + 4 b4 + 2 b3 + b2 (b_k the bits of L).
+// comp = 8 b5 + 4 b4 + 2 b3 + b2 (b_k the bits of L).  The partners at lane
+// distance 32 and 16 are reached with gfx950's permlane swaps: swapping the
+// upper half-wave (odd rows) of register a with the lower half-wave (even
+// rows) of register b leaves every lane holding its own kept value in one
+// register and its partner's in the other, so one swap and one add serve a
+// pair of components with no lane selects.
+__device__ __forceinline__ float add_swapped32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float add_swapped16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 template <int N>
 __device__ __forceinline__ void half_exchange(float (&v)[16], int lane, int bit) {
   const bool hi = (lane >> bit) & 1;
@@ -327,8 +342,10 @@ __device__ __forceinline__ float wave_reduce9(const float (&g)[9], int lane, int
   float v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) v[i] = i < 9 ? g[i] : 0.f;
-  half_exchange<8>(v, lane, 5);
-  half_exchange<4>(v, lane, 4);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = add_swapped32(v[i], v[i + 8]);  // lane distance 32
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = add_swapped16(v[i], v[i + 4]);  // lane distance 16
   half_exchange<2>(v, lane, 3);
   half_exchange<1>(v, lane, 2);
   float r = v[0];
