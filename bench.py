@@ -43,14 +43,17 @@ PROFILES = os.path.join(ROOT, "profiles", "traffic.json")
 
 def measured_traffic(kernel: str):
     """HBM bytes per dispatch of `kernel` from the committed counter profile,
-    or None when the kernel's source has changed since it was taken."""
+    or None when one of the kernel's source files has changed since it was
+    taken."""
     import hashlib
     try:
         rec = json.load(open(PROFILES))[kernel]
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec["sha256"]:
+    if h.hexdigest() != rec["sha256"]:
         return None
     return int(1024 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]))
 

@@ -1,0 +1,54 @@
+// Shared by the forward (raster.hip) and backward (raster_bwd.hip)
+// rasterizers: per-view launch parameters and the culling margin.  Both
+// kernels derive every pixel's FP32 offsets from these in the same way, so
+// the backward pass recomputes exactly the forward's decisions.
+#pragma once
+
+#include "gsup_internal.h"
+
+namespace gsup {
+namespace raster_detail {
+
+// One view of a batch: its raster, its first global tile id and the offset
+// of its first pixel in the concatenated outputs.
+struct RasterView {
+  int32_t width, height, tiles_x;
+  uint32_t tile_off;
+  int64_t pix_off;
+};
+
+struct RasterParams {
+  int32_t nv;
+  int64_t tiles;  // all views
+  float alpha_max, t_min;
+  float bg[3];
+  RasterView view[GS_MAX_VIEWS];
+};
+
+// Widening, in pixels, of a splat's support box in the per-wave culling test
+// (covers FP32 rounding of the box and of the per-pixel alpha test).
+constexpr float kCullMargin = 0.25f;
+
+inline RasterParams make_params(int32_t nv, const gs_camera* cams, const gs_raster_cfg& cfg) {
+  RasterParams p{};
+  p.nv = nv;
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < nv; ++v) {
+    RasterView& rv = p.view[v];
+    rv.width = cams[v].width;
+    rv.height = cams[v].height;
+    rv.tiles_x = (int32_t)ceil_div(cams[v].width, cfg.tile_size);
+    rv.tile_off = (uint32_t)tiles;
+    rv.pix_off = pix;
+    tiles += (int64_t)rv.tiles_x * ceil_div(cams[v].height, cfg.tile_size);
+    pix += (int64_t)cams[v].width * cams[v].height;
+  }
+  p.tiles = tiles;
+  p.alpha_max = cfg.alpha_max;
+  p.t_min = cfg.t_min;
+  for (int k = 0; k < 3; ++k) p.bg[k] = cfg.bg[k];
+  return p;
+}
+
+}  // namespace raster_detail
+}  // namespace gsup
