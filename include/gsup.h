@@ -14,12 +14,17 @@
  *   gs_upscale_hermite  low-res colour + derivatives -> high-res image, one
  *                       bicubic Hermite patch per low-res pixel cell.
  *
+ * Many views of one scene go through the *_views calls (one launch per step);
+ * training goes through gs_raster_grad_views_train and the *_backward_views
+ * calls; gs_fd_slopes provides the classical bicubic comparator.
+ *
  * Conventions shared by every call
  *   - Array arguments are DEVICE pointers (HBM), owned by the caller, dense
  *     row-major, little-endian, FP32 unless stated.  The library never
  *     allocates, frees or keeps device memory between calls.
- *   - Structs (gs_camera, gs_raster_cfg) and scalar out-parameters
- *     (n_pairs) live in HOST memory.
+ *   - Structs (gs_camera, gs_raster_cfg), camera arrays, size arrays and the
+ *     scalar out-parameter n_pairs live in HOST memory; n_pairs_dev is a
+ *     DEVICE pointer.
  *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *     Every call only enqueues work on that stream and returns, except
  *     gs_bin_sort, which waits on the stream once to read the pair count
