@@ -79,7 +79,7 @@ __device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
   Y[15] = -K3a * x * (xx - 3.f * yy);
 }
 
-template <int DEG>
+template <int DEG, bool MULTI>
 __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float* __restrict__ means,
                                                       const float* __restrict__ log_scales,
                                                       const float* __restrict__ quats,
@@ -88,30 +88,27 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
                                                       gs_splat* __restrict__ splats,
                                                       float* __restrict__ depth_out,
                                                       int4* __restrict__ rect_out) {
-  // Several views: the views of one chunk of Gaussians are adjacent logical
-  // blocks of one XCD, so the chunk's parameters are fetched into its L2 once.
-  int vi = 0;
-  int64_t chunk = blockIdx.x;
-  if (p.nv > 1) {
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    vi = (int)(lb % p.nv);
-    chunk = lb / p.nv;
-  }
-  const int64_t i = chunk * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
-  const ProjView& cv = p.view[vi];
-  const int64_t o = (int64_t)vi * p.n + i;  // output record
   constexpr int nb = (DEG + 1) * (DEG + 1);
 
+  // the Gaussian's parameters are read once for all views of a batch (the
+  // SH coefficients, read per view when on screen, come from the cache after
+  // the first view)
   const double mu0 = means[3 * i], mu1 = means[3 * i + 1], mu2 = means[3 * i + 2];
   const double ls0 = log_scales[3 * i], ls1 = log_scales[3 * i + 1], ls2 = log_scales[3 * i + 2];
   const float4 q4 = reinterpret_cast<const float4*>(quats)[i];
   const float sig = opacity[i];
 
-  bool ok = isfinite(sig) && isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(ls0) &&
-            isfinite(ls1) && isfinite(ls2) && isfinite(q4.x) && isfinite(q4.y) &&
-            isfinite(q4.z) && isfinite(q4.w);
+  const bool finite_in = isfinite(sig) && isfinite(mu0) && isfinite(mu1) && isfinite(mu2) &&
+                         isfinite(ls0) && isfinite(ls1) && isfinite(ls2) && isfinite(q4.x) &&
+                         isfinite(q4.y) && isfinite(q4.z) && isfinite(q4.w);
 
+  const int nv = MULTI ? p.nv : 1;  // one view: a single, fully specialised pass
+  for (int vi = 0; vi < nv; ++vi) {
+  const ProjView& cv = p.view[vi];
+  const int64_t o = (int64_t)vi * p.n + i;  // output record
+  bool ok = finite_in;
   const double* V = cv.V;
   // camera-space position, summed left to right (products of FP32 values are
   // exact in FP64, so the depth is the correctly ordered sum)
@@ -235,6 +232,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
   sf[2] = w1;
   depth_out[o] = dep;
   rect_out[o] = rect;
+  }
 }
 
 // Gradient of the SH colour sum_k Y_k(d) coef_k with respect to the unit
@@ -519,16 +517,23 @@ hipError_t launch_project(int64_t n, const float* means, const float* log_scales
                           float* depth, int32_t* rect, hipStream_t stream) {
   const ProjParams p = make_proj_params(n, nv, cams, cfg);
   const int threads = 256;
-  const int64_t chunks = ceil_div(n, threads);
-  const int64_t blocks = nv > 1 ? xcd_grid(chunks * nv) : chunks;
+  const int64_t blocks = ceil_div(n, threads);
   int4* r4 = reinterpret_cast<int4*>(rect);
   const dim3 g((unsigned)blocks), b(threads);
+#define GS_PROJ(D)                                                                              \
+  if (nv > 1)                                                                                   \
+    project_kernel<D, true><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh,     \
+                                                 splats, depth, r4);                            \
+  else                                                                                          \
+    project_kernel<D, false><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh,    \
+                                                  splats, depth, r4);
   switch (cfg.sh_degree) {
-    case 0: project_kernel<0><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
-    case 1: project_kernel<1><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
-    case 2: project_kernel<2><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
-    default: project_kernel<3><<<g, b, 0, stream>>>(p, means, log_scales, quats, opacity, sh, splats, depth, r4); break;
+    case 0: GS_PROJ(0) break;
+    case 1: GS_PROJ(1) break;
+    case 2: GS_PROJ(2) break;
+    default: GS_PROJ(3) break;
   }
+#undef GS_PROJ
   return hipGetLastError();
 }
 
