@@ -29,8 +29,9 @@
 // the wave leaves once every lane is done, and the workgroup stops fetching
 // batches once a barrier count shows no live pixel.  Splat means are held in
 // FP64 and turned into tile-relative FP32 offsets when staged into LDS, so
-// pixel - mean is exact at any image coordinate.  Blocks are renumbered so
-// that each XCD (own L2) works on a contiguous band of tiles.  Several views
+// pixel - mean is exact at any image coordinate.  List tiles are dealt to
+// the XCDs in turn, the workgroups of one list tile on one XCD (tile_block).
+// Several views
 // go through one launch: the grid covers the tiles of all views, numbered
 // view after view, and each workgroup finds its view from the tile id.
 #include "raster_common.h"
@@ -63,10 +64,10 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
   __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];  // per-wave hits, batch order
 
   // a workgroup covers one TILE x TILE part of a (TILE SUB)^2 list tile
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t tile = blk / (SUB * SUB);
+  int64_t tile;
+  int sub;
+  tile_block(blockIdx.x, SUB * SUB, tile, sub);
   if (tile >= p.tiles) return;
-  const int sub = (int)(blk % (SUB * SUB));
   int vi = 0;  // the view this tile belongs to (uniform over the block)
   while (vi + 1 < p.nv && (uint32_t)tile >= p.view[vi + 1].tile_off) ++vi;
   const int width = p.view[vi].width, height = p.view[vi].height, tiles_x = p.view[vi].tiles_x;
@@ -224,7 +225,7 @@ struct RasterOut {
 template <int TILE, bool GRAD, int BATCH, int SUB>
 void launch(const RasterParams& p, const gs_splat* splats, const int32_t* ids, const int2* ranges,
             const RasterOut& o, hipStream_t stream) {
-  const int64_t grid = xcd_grid(p.tiles * SUB * SUB);
+  const int64_t grid = tile_grid(p.tiles, SUB * SUB);
   raster_kernel<TILE, GRAD, BATCH, SUB><<<(unsigned)grid, TILE * TILE, 0, stream>>>(
       p, splats, ids, ranges, o.out, o.n_blend, o.state, o.last);
 }

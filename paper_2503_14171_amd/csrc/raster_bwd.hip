@@ -104,10 +104,10 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
   __shared__ int s_end;
 
   // the same workgroup-to-pixel layout as the forward (identical FP32 offsets)
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t tile = blk / (SUB * SUB);
+  int64_t tile;
+  int sub;
+  tile_block(blockIdx.x, SUB * SUB, tile, sub);
   if (tile >= p.tiles) return;
-  const int sub = (int)(blk % (SUB * SUB));
   int vi = 0;
   while (vi + 1 < p.nv && (uint32_t)tile >= p.view[vi + 1].tile_off) ++vi;
   const int width = p.view[vi].width, height = p.view[vi].height, tiles_x = p.view[vi].tiles_x;
@@ -278,7 +278,7 @@ void launch_bwd(int batch, const RasterParams& p, const gs_splat* splats, const 
                 const int2* ranges, const float4* state, const int32_t* last, const float* dout,
                 float* dsplat, hipStream_t stream) {
   constexpr int NT = TILE * TILE, LT = NT * SUB * SUB;
-  const unsigned grid = (unsigned)xcd_grid(p.tiles * SUB * SUB);
+  const unsigned grid = (unsigned)tile_grid(p.tiles, SUB * SUB);
   if (batch == LT / 4)
     raster_bwd_kernel<TILE, NT / 4, SUB><<<grid, NT, 0, stream>>>(p, splats, ids, ranges, state, last, dout, dsplat);
   else if (batch == LT / 2)

@@ -25,6 +25,22 @@ struct RasterParams {
   RasterView view[GS_MAX_VIEWS];
 };
 
+// Workgroup -> (list tile, sub-tile).  MI355X deals consecutive workgroups
+// round-robin to its 8 XCDs.  The SUB2 workgroups of one list tile share an
+// XCD (they stage the same list through its L2), and list tiles go to the
+// XCDs in turn, so every XCD gets dense and sparse screen regions alike: a
+// contiguous band of tiles per XCD leaves the XCDs holding the dense centre
+// of a frame working long after the others.  The grid is tile_grid(); tiles
+// at or beyond the real count are idle.
+inline int64_t tile_grid(int64_t tiles, int sub2) {
+  return (int64_t)kNumXcd * ceil_div(tiles, kNumXcd) * sub2;
+}
+__device__ __forceinline__ void tile_block(int64_t bid, int sub2, int64_t& tile, int& sub) {
+  const int64_t i = bid / kNumXcd;
+  tile = (i / sub2) * kNumXcd + bid % kNumXcd;
+  sub = (int)(i % sub2);
+}
+
 // Widening, in pixels, of a splat's support box in the per-wave culling test
 // (covers FP32 rounding of the box and of the per-pixel alpha test).
 constexpr float kCullMargin = 0.25f;
