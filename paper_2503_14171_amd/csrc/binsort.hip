@@ -4,8 +4,10 @@
 // (Sec. "Differentiable 3D Gaussian Splatting").  A tiled rasterizer needs
 // that order restricted to the splats that can reach each tile.  Instead of
 // sorting one 64-bit (tile, depth) key per pair, this implementation
-//   1. sorts the n splats once by their FP32 depth bits (stable LSD radix
-//      sort, so equal depths keep index order),
+//   1. sorts the splats that reach a tile (finite depth) once by their FP32
+//      depth bits (stable LSD radix sort, so equal depths keep index order;
+//      the first pass drops the +inf depths of splats without tiles and the
+//      top pass runs only for depth ranges wider than 8 binades),
 //   2. gathers the splats' tile rectangles in that order and sums their tile
 //      counts per block of 256 splats (one small scan gives every block's pair
 //      offset and the total K),
@@ -87,6 +89,34 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* excl, T* s_w) {
   return total;
 }
 
+// Exclusive scan, in place, of m elements by one workgroup of NT threads;
+// returns the total.  Rounds of NT * kItems elements: thread t loads
+// elements t, t + NT, ... of the round (coalesced: a wave reads 64
+// consecutive elements per load), then the stripes are scanned across the
+// block one after the other with a running carry.
+template <typename T, int NT>
+__device__ __forceinline__ T block_scan_inplace(T* __restrict__ data, int64_t m, T* s_w) {
+  T carry = 0;
+  for (int64_t base = 0; base < m; base += (int64_t)NT * kItems) {
+    T v[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = base + (int64_t)k * NT + threadIdx.x;
+      v[k] = i < m ? data[i] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (base + (int64_t)k * NT >= m) break;  // uniform over the block
+      const int64_t i = base + (int64_t)k * NT + threadIdx.x;
+      T excl;
+      const T tot = block_exclusive_scan<T, NT>(v[k], &excl, s_w);
+      if (i < m) data[i] = carry + excl;
+      carry += tot;
+    }
+  }
+  return carry;
+}
+
 template <typename T>
 __device__ __forceinline__ void load_blocked(const T* in, int64_t m, int64_t base, T (&v)[kItems]) {
   const int64_t s = base + (int64_t)threadIdx.x * kItems;
@@ -95,8 +125,9 @@ __device__ __forceinline__ void load_blocked(const T* in, int64_t m, int64_t bas
 }
 
 // Exclusive scan of m elements in one workgroup of 1024 threads (chunks of
-// 16384 with a carry); writes the grand total.  For the short arrays of
-// per-block sums.
+// 16384, kItems consecutive elements per thread, with a carry); writes the
+// grand total.  For the short arrays of per-block sums (on MI355X the
+// blocked layout measured faster here than the striped one above).
 constexpr int kSmallThreads = 1024;
 template <typename T>
 __global__ __launch_bounds__(kSmallThreads) void scan_small_kernel(T* __restrict__ data, int64_t m,
@@ -170,18 +201,122 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Depth-key passes.  A splat without tiles has the depth +inf; the first
+// pass drops those keys (they would only travel to the end of the order)
+// and records the min, max and count of the others.  Later passes sort
+// key - base, base = min with the first pass's digit bits cleared (so the
+// first pass's digit of key and of key - base agree); a pass whose digit is
+// zero for every key - base (its shift is at or above the bit length of
+// max - base) does nothing.  With the depth plan's widths (8, 9, 9, 6) that
+// skips the top pass whenever max - base < 2^26, which any set of depths
+// within a factor of 128 of each other satisfies, without the host reading
+// the range.  With info == nullptr a pass sorts plain keys.
+struct DepthKeys {
+  uint32_t* info = nullptr;  // device: [0] min kept key, [1] max kept key, [2] buffer of the last pass run
+  uint64_t* kept = nullptr;  // device: keys kept by the first pass
+  uint32_t* bstat = nullptr;  // device: first pass, per block (min, max, count, -) of its kept keys
+  uint32_t low_mask = 0;     // (1 << first pass width) - 1
+  int first = 0;             // this is the first pass
+  int out_index = 0;         // ping-pong buffer this pass writes (recorded in info[2])
+};
+constexpr uint32_t kInfBits = 0x7F800000u;
+
+__device__ __forceinline__ uint32_t depth_base(const DepthKeys& dk) {
+  return (dk.info && !dk.first) ? (dk.info[0] & ~dk.low_mask) : 0u;
+}
+
+__device__ __forceinline__ bool pass_is_identity(const DepthKeys& dk, int shift) {
+  if (!dk.info || dk.first) return false;
+  const uint32_t base = depth_base(dk), hi = dk.info[1];
+  const int bits = hi > base ? 32 - __clz(hi - base) : 0;
+  return shift >= bits;
+}
+
+__device__ __forceinline__ bool key_kept(const DepthKeys& dk, uint32_t key) {
+  return !dk.first || key != kInfBits;
+}
+
+// Min, max and count of a block's kept keys (first pass) to bstat[block];
+// the pass's scan reduces them.  No atomics: thousands of them on one
+// address serialise in L2.
+__device__ __forceinline__ void record_kept_keys(const DepthKeys& dk, uint32_t lo, uint32_t hi,
+                                                 uint32_t count, uint4* s_stat) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+    count += (uint32_t)__shfl_xor((int)count, d, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_stat[wave] = make_uint4(lo, hi, count, 0u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint4 r = s_stat[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) {
+      r.x = min(r.x, s_stat[w].x);
+      r.y = max(r.y, s_stat[w].y);
+      r.z += s_stat[w].z;
+    }
+    reinterpret_cast<uint4*>(dk.bstat)[blockIdx.x] = r;
+  }
+}
+
+// First pass: min, max and count over the blocks' records into info / kept.
+__device__ __forceinline__ void reduce_kept_keys(const DepthKeys& dk, int64_t nblocks) {
+  __shared__ uint32_t s_lo[kWaves], s_hi[kWaves];
+  __shared__ uint64_t s_n[kWaves];
+  uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+  uint64_t cnt = 0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) {
+    const uint4 r = reinterpret_cast<const uint4*>(dk.bstat)[b];
+    lo = min(lo, r.x);
+    hi = max(hi, r.y);
+    cnt += r.z;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+    cnt += __shfl_xor(cnt, d, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_lo[wave] = lo;
+    s_hi[wave] = hi;
+    s_n[wave] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) {
+      lo = min(lo, s_lo[w]);
+      hi = max(hi, s_hi[w]);
+      cnt += s_n[w];
+    }
+    dk.info[0] = lo;
+    dk.info[1] = hi;
+    dk.info[2] = 0u;
+    dk.kept[0] = cnt;
+  }
+}
+
 template <int BITS>
 __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t* __restrict__ keys,
                                                                  int64_t m, const uint64_t* m_dev,
                                                                  int64_t cap, int shift,
                                                                  uint32_t* __restrict__ hist,
-                                                                 int64_t nblocks) {
+                                                                 int64_t nblocks, DepthKeys dk) {
   constexpr int R = 1 << BITS;
   __shared__ uint32_t s_h[kWaves][R];
+  __shared__ uint4 s_stat[kWaves];
+  if (pass_is_identity(dk, shift)) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (m_dev) m = eff_count(m_dev, cap);
   if ((int64_t)blockIdx.x * kTile >= m) {  // past the data: an empty column
     for (int d = t; d < R; d += kThreads) hist[(int64_t)d * nblocks + blockIdx.x] = 0u;
+    if (dk.first && t == 0)
+      reinterpret_cast<uint4*>(dk.bstat)[blockIdx.x] = make_uint4(0xFFFFFFFFu, 0u, 0u, 0u);
     return;
   }
   for (int k = t; k < kWaves * R; k += kThreads) (&s_h[0][0])[k] = 0;
@@ -194,13 +329,21 @@ __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t*
   }
   __syncthreads();
   const uint64_t lt = lanes_below(lane);
+  const uint32_t base = depth_base(dk);
+  uint32_t lo = 0xFFFFFFFFu, hi = 0u, kept = 0u;
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
-    const bool valid = seg + r * 64 + lane < m;
-    const uint32_t d = (key[r] >> shift) & (R - 1);
+    const bool valid = seg + r * 64 + lane < m && key_kept(dk, key[r]);
+    const uint32_t d = ((key[r] - base) >> shift) & (R - 1);
     const uint64_t same = match_digit<BITS>(d, valid);
     if (valid && (same & lt) == 0) s_h[wave][d] += (uint32_t)__popcll(same);
+    if (valid) {
+      lo = min(lo, key[r]);
+      hi = max(hi, key[r]);
+      ++kept;
+    }
   }
+  if (dk.first) record_kept_keys(dk, lo, hi, kept, s_stat);
   __syncthreads();
   for (int d = t; d < R; d += kThreads) {
     uint32_t c = 0;
@@ -213,27 +356,13 @@ __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t*
 // Block d scans row d of hist (nblocks entries) in place and writes its total.
 __global__ __launch_bounds__(kThreads) void hist_scan_kernel(uint32_t* __restrict__ hist,
                                                              int64_t nblocks,
-                                                             uint32_t* __restrict__ totals) {
+                                                             uint32_t* __restrict__ totals,
+                                                             DepthKeys dk, int shift) {
   __shared__ uint32_t s_w[kWaves];
+  if (pass_is_identity(dk, shift)) return;
+  if (dk.first && blockIdx.x == 0) reduce_kept_keys(dk, nblocks);
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < nblocks; base += kTile) {
-    uint32_t v[kItems];
-    load_blocked(row, nblocks, base, v);
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) sum += v[k];
-    uint32_t excl;
-    const uint32_t tot = block_exclusive_scan<uint32_t>(sum, &excl, s_w);
-    uint32_t run = carry + excl;
-    const int64_t s0 = base + (int64_t)threadIdx.x * kItems;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      if (s0 + k < nblocks) row[s0 + k] = run;
-      run += v[k];
-    }
-    carry += tot;
-  }
+  const uint32_t carry = block_scan_inplace<uint32_t, kThreads>(row, nblocks, s_w);
   if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
@@ -242,10 +371,12 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in /* null: index */,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t m,
     const uint64_t* m_dev, int64_t cap, int shift, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ totals, int64_t nblocks) {
+    const uint32_t* __restrict__ totals, int64_t nblocks, DepthKeys dk) {
   constexpr int R = 1 << BITS;
+  if (pass_is_identity(dk, shift)) return;
   if (m_dev) m = eff_count(m_dev, cap);
   if ((int64_t)blockIdx.x * kTile >= m) return;
+  if (dk.info && blockIdx.x == 0 && threadIdx.x == 0) dk.info[2] = (uint32_t)dk.out_index;
   constexpr int DPT = R > kThreads ? R / kThreads : 1;  // digits per thread in the digit phases
   __shared__ uint32_t s_keys[kTile];
   __shared__ uint32_t s_vals[kTile];
@@ -253,8 +384,10 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   __shared__ uint32_t s_gbase[R];
   __shared__ uint32_t s_lstart[R];
   __shared__ uint32_t s_w[kWaves];
+  __shared__ uint32_t s_count;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint32_t kbase = depth_base(dk);
   const int64_t base = (int64_t)blockIdx.x * kTile;
   const int64_t seg = base + wave * kSeg;
   for (int k = t; k < kWaves * R; k += kThreads) (&s_wh[0][0])[k] = 0;
@@ -287,12 +420,14 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   }
   __syncthreads();
 
-  // 1. rank within the wave's segment
+  // 1. rank within the wave's segment (dropped keys take no rank)
   const uint64_t lt = lanes_below(lane);
+  bool kept[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
-    const bool valid = seg + r * 64 + lane < m;
-    const uint32_t d = (key[r] >> shift) & (R - 1);
+    const bool valid = seg + r * 64 + lane < m && key_kept(dk, key[r]);
+    kept[r] = valid;
+    const uint32_t d = ((key[r] - kbase) >> shift) & (R - 1);
     const uint64_t same = match_digit<BITS>(d, valid);
     const uint32_t below = (uint32_t)__popcll(same & lt);
     const uint32_t old = s_wh[wave][d];
@@ -316,7 +451,8 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
       sum += tot[k];
     }
     uint32_t excl;
-    block_exclusive_scan<uint32_t>(sum, &excl, s_w);
+    const uint32_t kept_total = block_exclusive_scan<uint32_t>(sum, &excl, s_w);
+    if (t == 0) s_count = kept_total;
 #pragma unroll
     for (int k = 0; k < DPT; ++k) {
       const int d = t * DPT + k;
@@ -337,8 +473,8 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   // 3. reorder the block in LDS by digit
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
-    if (seg + r * 64 + lane < m) {
-      const uint32_t d = (key[r] >> shift) & (R - 1);
+    if (kept[r]) {
+      const uint32_t d = ((key[r] - kbase) >> shift) & (R - 1);
       const uint32_t pos = s_wh[wave][d] + rank[r];
       s_keys[pos] = key[r];
       s_vals[pos] = val[r];
@@ -347,12 +483,12 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   __syncthreads();
 
   // 4. digit runs are contiguous: consecutive threads write consecutive addresses
-  const int count = (m - base < kTile) ? (int)(m - base) : kTile;
+  const int count = (int)s_count;
   for (int i = t; i < count; i += kThreads) {
     const uint32_t k = s_keys[i];
-    const uint32_t d = (k >> shift) & (R - 1);
+    const uint32_t d = ((k - kbase) >> shift) & (R - 1);
     const uint32_t dst = s_gbase[d] + (uint32_t)i - s_lstart[d];
-    keys_out[dst] = k;
+    if (keys_out) keys_out[dst] = k;  // null: values only (no later pass reads the keys)
     vals_out[dst] = s_vals[i];
   }
 }
@@ -362,30 +498,31 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
 template <int BITS>
 hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                            uint32_t* vout, int64_t m, const uint64_t* m_dev, int shift,
-                           uint32_t* hist, uint32_t* totals, hipStream_t stream) {
+                           uint32_t* hist, uint32_t* totals, const DepthKeys& dk,
+                           hipStream_t stream) {
   const int64_t nb = std::max<int64_t>(ceil_div(m, kTile), 1);
   radix_upsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, m, m_dev, m, shift, hist,
-                                                                     nb);
+                                                                     nb, dk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hist_scan_kernel<<<1u << BITS, kThreads, 0, stream>>>(hist, nb, totals);
+  hist_scan_kernel<<<1u << BITS, kThreads, 0, stream>>>(hist, nb, totals, dk, shift);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   radix_downsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(
-      kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb);
+      kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb, dk);
   return hipGetLastError();
 }
 
 // One stable pass over `bits` (1..kMaxAnyDigitBits) bits starting at `shift`.
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       int64_t m, const uint64_t* m_dev, int shift, int bits, uint32_t* hist,
-                      uint32_t* totals, hipStream_t stream) {
+                      uint32_t* totals, const DepthKeys& dk, hipStream_t stream) {
   switch (bits) {
 #define GS_RADIX_CASE(B)                                                                  \
   case B:                                                                                 \
     if (B <= kMaxAnyDigitBits)                                                            \
       return radix_pass_bits<(B <= kMaxAnyDigitBits ? B : 1)>(kin, vin, kout, vout, m, m_dev, \
-                                                           shift, hist, totals, stream);  \
+                                                           shift, hist, totals, dk, stream); \
     break;
     GS_RADIX_CASE(1)
     GS_RADIX_CASE(2)
@@ -412,6 +549,21 @@ int radix_plan(int bits, int widths[8], int max_bits = kMaxDigitBits) {
   return passes;
 }
 
+// Digit widths of the depth sort: the first pass (over every splat) at the
+// common width, the next two at the tile digit's width, so that depths
+// spanning fewer than 2^26 ulps (8 binades) need three passes; the fourth
+// pass covers the rest of the 32 bits.
+int depth_plan(int widths[8]) {
+  if (kMaxDigitBits == 8 && kMaxTileDigitBits == 9) {
+    widths[0] = 8;
+    widths[1] = 9;
+    widths[2] = 9;
+    widths[3] = 6;
+    return 4;
+  }
+  return radix_plan(32, widths);
+}
+
 // ----------------------------------------------------------------------------
 // binning kernels
 // ----------------------------------------------------------------------------
@@ -432,27 +584,27 @@ __device__ __forceinline__ int view_of(const ViewTiles& vt, uint32_t e) {
 }
 
 // Rectangles in depth order (clipped to their view's tile grid) and, per
-// block of kEmit splats, the sum of their tile counts.  Splats with an
-// infinite depth (the projection's mark for "reaches no tile") sort last and
-// get an empty rectangle without the random read of theirs.
-constexpr uint32_t kInfBits = 0x7F800000u;
+// block of kEmit splats, the sum of their tile counts.  The depth sort left
+// only the splats with a finite depth (kept[0] of them) in the order buffer
+// that its last pass wrote (dinfo[2]).
 __global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
-                                                            const uint32_t* __restrict__ order,
-                                                            const uint32_t* __restrict__ skeys,
+                                                            const uint32_t* __restrict__ order0,
+                                                            const uint32_t* __restrict__ order1,
+                                                            const uint32_t* __restrict__ dinfo,
+                                                            const uint64_t* kept,
                                                             const int4* __restrict__ rect,
                                                             ViewTiles vt,
                                                             int4* __restrict__ srect,
                                                             uint64_t* __restrict__ bsum) {
   __shared__ uint64_t s_w[kEmit / 64];
+  const int64_t nk = eff_count(kept, n);
+  const uint32_t* __restrict__ order = dinfo[2] ? order1 : order0;
   const int64_t p = (int64_t)blockIdx.x * kEmit + threadIdx.x;
   uint64_t c = 0;
-  if (p < n) {
-    int4 r = make_int4(0, 0, 0, 0);
-    if (skeys[p] != kInfBits) {
-      const uint32_t e = order[p];
-      const int v = view_of(vt, e);
-      r = clip_rect(rect[e], vt.tiles_x[v], vt.tiles_y[v]);
-    }
+  if (p < nk) {
+    const uint32_t e = order[p];
+    const int v = view_of(vt, e);
+    const int4 r = clip_rect(rect[e], vt.tiles_x[v], vt.tiles_y[v]);
     srect[p] = r;
     c = rect_tiles(r);
   }
@@ -468,7 +620,10 @@ __global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
 // the writes are coalesced whatever the splats' tile counts.  Tile keys are
 // global: view v's tiles are numbered from tile_off[v].  With `total` set
 // (device-side count) nothing is written unless the total fits `cap`.
-__global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* __restrict__ order,
+__global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* __restrict__ order0,
+                                                     const uint32_t* __restrict__ order1,
+                                                     const uint32_t* __restrict__ dinfo,
+                                                     const uint64_t* kept,
                                                      const int4* __restrict__ srect,
                                                      const uint64_t* __restrict__ boff,
                                                      ViewTiles vt, const uint64_t* total,
@@ -480,8 +635,11 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
   __shared__ uint32_t s_gid[kEmit];
   __shared__ uint32_t s_w[kEmit / 64];
   const int t = threadIdx.x;
+  const int64_t nk = eff_count(kept, n);
+  const uint32_t* __restrict__ order = dinfo[2] ? order1 : order0;
   const int64_t p0 = (int64_t)blockIdx.x * kEmit;
-  const int nb = (int)((n - p0 < kEmit) ? (n - p0) : kEmit);
+  const int64_t left = nk - p0;
+  const int nb = left <= 0 ? 0 : (left < kEmit ? (int)left : kEmit);
   uint32_t c = 0;
   if (t < nb) {
     const int4 r = srect[p0 + t];
@@ -625,6 +783,8 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles) {
   p.off_hist = take(sizeof(uint32_t) * (size_t)((int64_t(1) << kMaxAnyDigitBits) * max_blocks));
   p.off_totals = take(sizeof(uint32_t) * (size_t)(1 << kMaxAnyDigitBits));
   p.off_total = take(sizeof(uint64_t));
+  p.off_dinfo = take(4 * sizeof(uint32_t) + sizeof(uint64_t));
+  p.off_bstat = take(4 * sizeof(uint32_t) * (size_t)ceil_div(n1, kTile));
   p.bytes = off;
   return p;
 }
@@ -657,30 +817,44 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
     return check_hip(hipGetLastError(), "fill_i32_kernel");
   }
-  // 1. depth order of all splats: stable LSD radix sort of the FP32 depth bits
-  //    (positive floats order like their bits; +inf marks splats without
-  //    tiles); the first pass reads the depths in place and numbers them.
-  //    Several views sort together: a tile only ever holds splats of one
-  //    view, so the global order restricted to a tile is that view's order.
+  // 1. depth order of the splats with tiles: stable LSD radix sort of the
+  //    FP32 depth bits (positive floats order like their bits; +inf marks
+  //    splats without tiles, which the first pass drops); the first pass
+  //    reads the depths in place and numbers them, the later ones sort
+  //    depth - base and skip themselves where the depth range is narrower
+  //    than their digit (DepthKeys).  Several views sort together: a tile
+  //    only ever holds splats of one view, so the global order restricted to
+  //    a tile is that view's order.
+  uint32_t* dinfo = u32(p.off_dinfo);
+  uint64_t* kept = reinterpret_cast<uint64_t*>(ws + p.off_dinfo + 16);
+  const uint64_t* kept_count = kept;
   int widths[8];
-  int passes = radix_plan(32, widths);
+  const int passes_depth = depth_plan(widths);
   int cur = 0, shift = 0;
-  for (int k = 0; k < passes; ++k) {
+  for (int k = 0; k < passes_depth; ++k) {
     const uint32_t* kin = k == 0 ? reinterpret_cast<const uint32_t*>(depth) : u32(p.off_gkey[cur]);
     const uint32_t* vin = k == 0 ? nullptr : u32(p.off_gval[cur]);
-    GS_TRY(radix_pass(kin, vin, u32(p.off_gkey[cur ^ 1]), u32(p.off_gval[cur ^ 1]), n, nullptr,
-                      shift, widths[k], hist, totals, stream),
+    DepthKeys dk;
+    dk.info = dinfo;
+    dk.kept = kept;
+    dk.bstat = u32(p.off_bstat);
+    dk.low_mask = (1u << widths[0]) - 1u;
+    dk.first = k == 0;
+    dk.out_index = cur ^ 1;
+    GS_TRY(radix_pass(kin, vin, u32(p.off_gkey[cur ^ 1]), u32(p.off_gval[cur ^ 1]), n,
+                      k == 0 ? nullptr : kept_count, shift, widths[k], hist, totals, dk, stream),
            "depth radix pass");
     shift += widths[k];
     cur ^= 1;
   }
-  const uint32_t* order = u32(p.off_gval[cur]);
-  const uint32_t* skeys = u32(p.off_gkey[cur]);
+  const uint32_t* order0 = u32(p.off_gval[0]);
+  const uint32_t* order1 = u32(p.off_gval[1]);
 
   // 2. rectangles in depth order, pair offsets per block of splats, total K
   int4* srect = reinterpret_cast<int4*>(ws + p.off_srect);
   const int64_t nbe = ceil_div(n, kEmit);
-  gather_rect_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, skeys, r4, vt, srect, bsum);
+  gather_rect_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, dinfo, kept_count, r4,
+                                                           vt, srect, bsum);
   GS_TRY(hipGetLastError(), "gather_rect_kernel");
   scan_small_kernel<uint64_t><<<1, kSmallThreads, 0, stream>>>(bsum, nbe, total);
   GS_TRY(hipGetLastError(), "pair offset scan");
@@ -704,22 +878,24 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
   GS_TRY(hipGetLastError(), "fill_i32_kernel");
   if (m == 0) return GS_OK;
-  passes = radix_plan(p.tile_bits, widths, kMaxTileDigitBits);
+  const int passes = radix_plan(p.tile_bits, widths, kMaxTileDigitBits);
   // values end in sorted_ids after `passes` ping-pong steps
   uint32_t* vbuf[2];
   vbuf[0] = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(sorted_ids) : u32(p.off_pval);
   vbuf[1] = (passes % 2 == 0) ? u32(p.off_pval) : reinterpret_cast<uint32_t*>(sorted_ids);
   uint32_t* kbuf[2] = {u32(p.off_pkey[0]), u32(p.off_pkey[1])};
-  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order, srect, bsum, vt, m_dev, p.capacity,
-                                                   kbuf[0], vbuf[0]);
+  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, dinfo, kept_count, srect,
+                                                   bsum, vt, m_dev, p.capacity, kbuf[0], vbuf[0]);
   GS_TRY(hipGetLastError(), "emit_kernel");
 
   // 4. stable sort of the pairs by tile id
   cur = 0;
   shift = 0;
   for (int k = 0; k < passes; ++k) {
-    GS_TRY(radix_pass(kbuf[cur], vbuf[cur], kbuf[cur ^ 1], vbuf[cur ^ 1], m, m_dev, shift,
-                      widths[k], hist, totals, stream),
+    // the keys of the last pass are only needed by tile_range_kernel
+    uint32_t* kout = (k + 1 == passes && passes == 1) ? nullptr : kbuf[cur ^ 1];
+    GS_TRY(radix_pass(kbuf[cur], vbuf[cur], kout, vbuf[cur ^ 1], m, m_dev, shift,
+                      widths[k], hist, totals, DepthKeys{}, stream),
            "tile radix pass");
     shift += widths[k];
     cur ^= 1;

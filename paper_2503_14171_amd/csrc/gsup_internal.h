@@ -69,6 +69,8 @@ struct BinSortPlan {
   size_t off_hist;                  // radix digit counts [2^digit bits * max blocks]
   size_t off_totals;                // per-digit totals
   size_t off_total;                 // 1 x uint64 pair total
+  size_t off_dinfo;                 // depth keys: min, max, last buffer (4 x u32), kept count (u64)
+  size_t off_bstat;                 // depth keys: per-block min, max, count of the first pass
   size_t bytes = 0;
 };
 BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles);

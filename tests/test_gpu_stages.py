@@ -146,6 +146,63 @@ def test_bin_sort_stable_under_depth_ties(gs, oracle, seed):
     np.testing.assert_array_equal(ids, ref_ids)
 
 
+_DEPTH_KINDS = ["full_range", "narrow", "eight_binades", "just_over_eight_binades", "mostly_culled",
+                "one_kept", "all_equal", "denormal_and_huge"]
+
+
+def _depth_set(kind, rng, n):
+    f32 = np.float32
+    if kind == "full_range":  # every positive finite float: all four passes
+        return rng.integers(1, 0x7F800000, n, dtype=np.uint32).view(f32)
+    if kind == "narrow":  # 300 ulps: only the first two digits vary
+        return (np.uint32(0x3F800000) + rng.integers(0, 300, n, dtype=np.uint32)).view(f32)
+    if kind == "eight_binades":  # [1, 256): max - min < 2^26 ulps, top pass skipped
+        return np.exp2(rng.uniform(0.0, 8.0, n)).astype(f32).clip(1.0, np.nextafter(f32(256), f32(0)))
+    if kind == "just_over_eight_binades":  # [1, 256]: exactly 2^26 ulps, top pass needed
+        d = np.exp2(rng.uniform(0.0, 8.0, n)).astype(f32).clip(1.0, 256.0)
+        d[rng.choice(n, 5, replace=False)] = f32(256.0)
+        d[rng.choice(n, 5, replace=False)] = f32(1.0)
+        return d
+    if kind == "mostly_culled":
+        d = rng.uniform(0.5, 40.0, n).astype(f32)
+        d[rng.random(n) < 0.9] = np.inf
+        return d
+    if kind == "one_kept":
+        d = np.full(n, np.inf, f32)
+        d[n // 3] = f32(4.0)
+        return d
+    if kind == "all_equal":
+        return np.full(n, 2.5, f32)
+    if kind == "denormal_and_huge":
+        return rng.choice(np.array([1e-42, 1e-38, 1e-30, 0.25, 3.0, 1e30, 3.4e38], f32), n)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", _DEPTH_KINDS)
+def test_bin_sort_depth_key_ranges(gs, oracle, kind):
+    """Depth sets that need one to four radix passes over their bit range,
+    with and without culled (+inf) splats, whose rectangles are empty as the
+    projection leaves them: the lists must equal a lexicographic sort."""
+    from paper_2503_14171_amd import scenes
+    rng = np.random.default_rng(_DEPTH_KINDS.index(kind) + 40)
+    n = 70000
+    cam = scenes.make_camera(512, 384)
+    cfg = scenes.render_config(0, tile_size=16)
+    tx, ty = _tiles_xy(cam, 16)
+    x0 = rng.integers(0, tx, n)
+    y0 = rng.integers(0, ty, n)
+    w = rng.integers(1, 3, n)
+    h = rng.integers(1, 3, n)
+    rect = np.stack([x0, y0, np.minimum(x0 + w, tx), np.minimum(y0 + h, ty)], 1).astype(np.int32)
+    d32 = _depth_set(kind, rng, n)
+    rect[np.isinf(d32)] = 0
+    print(f"bin_sort depth keys kind={kind}", flush=True)
+    ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
+    ref_ids, ref_ranges = oracle.tile_lists(d32, rect, tx, ty)
+    np.testing.assert_array_equal(ranges, ref_ranges)
+    np.testing.assert_array_equal(ids, ref_ids)
+
+
 def test_bin_sort_capacity_error_and_empty(gs, oracle):
     import torch
     from paper_2503_14171_amd import scenes
