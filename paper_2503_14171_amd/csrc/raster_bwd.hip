@@ -46,7 +46,9 @@ namespace {
 // upper half-wave (odd rows) of register a with the lower half-wave (even
 // rows) of register b leaves every lane holding its own kept value in one
 // register and its partner's in the other, so one swap and one add serve a
-// pair of components with no lane selects.
+// pair of components with no lane selects.  The steps inside a row of 16
+// lanes pair lanes by DPP (mirror images in the row, the half-row, then the
+// quad), which also differ in the bit that decides the kept half.
 __device__ __forceinline__ float add_swapped32(float a, float b) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
@@ -57,14 +59,24 @@ __device__ __forceinline__ float add_swapped16(float a, float b) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-template <int N>
+// A lane's copy of another lane's value by a DPP operand modifier (a VALU
+// move, no LDS round trip as for ds_bpermute); CTRL is the GFX9 dpp_ctrl.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+// Partner lanes by DPP within a row of 16: row_mirror (0x140) pairs i with
+// 15 - i (different bit 3), row_half_mirror (0x141) pairs i with 7 - i
+// (different bit 2); both keep bits 4 and 5.
+template <int N, int CTRL>
 __device__ __forceinline__ void half_exchange(float (&v)[16], int lane, int bit) {
   const bool hi = (lane >> bit) & 1;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     const float send = hi ? v[i] : v[i + N];
     const float keep = hi ? v[i + N] : v[i];
-    v[i] = keep + __shfl_xor(send, 1 << bit, 64);
+    v[i] = keep + dpp_mov<CTRL>(send);
   }
 }
 
@@ -76,11 +88,11 @@ __device__ __forceinline__ float wave_reduce9(const float (&g)[9], int lane, int
   for (int i = 0; i < 8; ++i) v[i] = add_swapped32(v[i], v[i + 8]);  // lane distance 32
 #pragma unroll
   for (int i = 0; i < 4; ++i) v[i] = add_swapped16(v[i], v[i + 4]);  // lane distance 16
-  half_exchange<2>(v, lane, 3);
-  half_exchange<1>(v, lane, 2);
+  half_exchange<2, 0x140>(v, lane, 3);
+  half_exchange<1, 0x141>(v, lane, 2);
   float r = v[0];
-  r += __shfl_xor(r, 2, 64);
-  r += __shfl_xor(r, 1, 64);
+  r += dpp_mov<0x4E>(r);  // quad_perm [2, 3, 0, 1]
+  r += dpp_mov<0xB1>(r);  // quad_perm [1, 0, 3, 2]
   comp = (((lane >> 5) & 1) << 3) | (((lane >> 4) & 1) << 2) | (((lane >> 3) & 1) << 1) |
          ((lane >> 2) & 1);
   return r;
@@ -97,7 +109,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
   constexpr float kHalfLog2e = 0.72134752044448170368f;
   __shared__ float4 s_a[BATCH];   // mean x, mean y (tile-relative), conic a, conic b
   __shared__ float4 s_b[BATCH];   // conic c, log2 sigma, support, red
-  __shared__ float4 s_c[BATCH];   // green, blue, sigma, -
+  __shared__ float4 s_c[BATCH];   // green, blue, 1 / sigma, -
   __shared__ int32_t s_id[BATCH];
   __shared__ uint32_t s_mask[NW > 1 ? BATCH : 1];
   __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
       const float mx = (float)(m.x - ox), my = (float)(m.y - oy);
       s_a[t] = make_float4(mx, my, q.x, q.y);
       s_b[t] = make_float4(q.z, log2f(q.w), c.w, c.x);
-      s_c[t] = make_float4(c.y, c.z, q.w, 0.f);
+      s_c[t] = make_float4(c.y, c.z, 1.f / q.w, 0.f);
       s_id[t] = id;
       if (NW > 1) {
         const float det = q.x * q.z - q.y * q.y;
@@ -216,15 +228,16 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
       for (int f = 0; f < 9; ++f) g[f] = 0.f;
       if (act) {
         const float4 gc = s_c[j];
-        const float cr = gb.w, cg = gc.x, cb = gc.y, sig = gc.z;
+        const float cr = gb.w, cg = gc.x, cb = gc.y, inv_sig = gc.z;
         float alpha = __builtin_amdgcn_exp2f(fmaf(q, -kHalfLog2e, gb.y));
         const bool clamp = alpha > p.alpha_max;
         alpha = clamp ? p.alpha_max : alpha;
         const float ax = clamp ? 0.f : -alpha * u;
         const float ay = clamp ? 0.f : -alpha * v;
         const float axy = clamp ? 0.f : alpha * fmaf(u, v, -ga.w);
-        // state before this fragment
-        const float om = 1.f / (1.f - alpha);
+        // state before this fragment (1 / (1 - alpha) by the hardware reciprocal:
+        // 1 ulp, and 1 - alpha >= 1 - alpha_max is far from zero)
+        const float om = __builtin_amdgcn_rcpf(1.f - alpha);
         T = T * om;
         Tx = fmaf(T, ax, Tx) * om;
         Ty = fmaf(T, ay, Ty) * om;
@@ -261,7 +274,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
           g[2] = fmaf(-0.5f * aE, dx * dx, dx * Fu);                 // conic a
           g[3] = fmaf(-aE, dx * dy, fmaf(dy, Fu, fmaf(dx, Fv, -alpha * dAxy)));  // conic b
           g[4] = fmaf(-0.5f * aE, dy * dy, dy * Fv);                 // conic c
-          g[5] = aE / sig;                                           // opacity
+          g[5] = aE * inv_sig;                                       // opacity
         }
       }
       if (__ballot(act) != 0) {
