@@ -21,12 +21,15 @@
 // workgroups that share its list), one pixel per lane, and every wave64 owns one 8x8
 // quadrant of the tile.  The tile's splats stream through LDS in batches of up to one
 // splat per thread (BATCH = TILE^2, or TILE^2/2, TILE^2/4); while staging, each thread marks the quadrants its splat's
-// support box meets, and each wave then compacts the batch (ballot + prefix
+// support ellipse reaches (its box, then the exact minimum of d^T Q d over the
+// quadrant: a third of the box hits have no pixel above alpha_min), and each
+// wave then compacts the batch (ballot + prefix
 // popcount) into its own LDS list of hits in depth order, so a wave only
 // evaluates splats that can reach its 64 pixels.  Every lane reads the same
 // LDS record (broadcast, no bank conflicts).  A lane whose transmittance
-// dropped below t_min leaves the loop; the wave's exec mask then shrinks and
-// the wave leaves once every lane is done, and the workgroup stops fetching
+// dropped below t_min blends nothing more (it still takes the loop's uniform
+// steps, which costs less than masking it out), the wave leaves the loop once
+// every lane is done, and the workgroup stops fetching
 // batches once a barrier count shows no live pixel.  Splat means are held in
 // FP64 and turned into tile-relative FP32 offsets when staged into LDS, so
 // pixel - mean is exact at any image coordinate.  List tiles are dealt to
@@ -117,8 +120,12 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
           const int qx1 = min(QX - 1, (int)floorf((mx + rx) * 0.125f));
           const int qy0 = max(0, (int)ceilf((my - ry - 7.f) * 0.125f));
           const int qy1 = min(QX - 1, (int)floorf((my + ry) * 0.125f));
+          const bool exact = q.x > 0.f && q.z > 0.f;
+          const float ia = exact ? 1.f / q.x : 0.f, ic = exact ? 1.f / q.z : 0.f;
           for (int qy = qy0; qy <= qy1; ++qy)
-            for (int qx = qx0; qx <= qx1; ++qx) mask |= 1u << (qy * QX + qx);
+            for (int qx = qx0; qx <= qx1; ++qx)
+              if (!exact || quad_reaches(mx, my, q.x, q.y, q.z, ia, ic, c.w, 8.f * qx, 8.f * qy))
+                mask |= 1u << (qy * QX + qx);
         } else {
           mask = (NW >= 32) ? ~0u : ((1u << NW) - 1u);  // degenerate in FP32: keep everywhere
         }
@@ -144,7 +151,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
     }
     if (!done) {
       for (int k = 0; k < nl; ++k) {
-        if (!done) {
+        {
           const int j = NW > 1 ? (int)s_list[wave][k] : k;
           const float4 ga = s_a[j];
           const float4 gb = s_b[j];
@@ -152,7 +159,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
           const float u = fmaf(ga.z, dx, ga.w * dy);  // (Q d)_x
           const float v = fmaf(ga.w, dx, gb.x * dy);  // (Q d)_y
           const float q = fmaf(dx, u, dy * v);        // d^T Q d
-          if (q <= gb.z) {                            // alpha >= alpha_min
+          if (!done && q <= gb.z) {                   // alpha >= alpha_min
             const float2 gc = s_c[j];
             // the exponent is >= log2(alpha_min) > -126: no denormal handling needed
             float alpha = __builtin_amdgcn_exp2f(fmaf(q, -kHalfLog2e, gb.y));

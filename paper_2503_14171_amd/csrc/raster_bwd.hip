@@ -191,8 +191,12 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
           const int qx1 = min(QX - 1, (int)floorf((mx + rx) * 0.125f));
           const int qy0 = max(0, (int)ceilf((my - ry - 7.f) * 0.125f));
           const int qy1 = min(QX - 1, (int)floorf((my + ry) * 0.125f));
+          const bool exact = q.x > 0.f && q.z > 0.f;
+          const float ia = exact ? 1.f / q.x : 0.f, ic = exact ? 1.f / q.z : 0.f;
           for (int qy = qy0; qy <= qy1; ++qy)
-            for (int qx = qx0; qx <= qx1; ++qx) mask |= 1u << (qy * QX + qx);
+            for (int qx = qx0; qx <= qx1; ++qx)
+              if (!exact || quad_reaches(mx, my, q.x, q.y, q.z, ia, ic, c.w, 8.f * qx, 8.f * qy))
+                mask |= 1u << (qy * QX + qx);
         } else {
           mask = (NW >= 32) ? ~0u : ((1u << NW) - 1u);
         }

@@ -45,6 +45,29 @@ __device__ __forceinline__ void tile_block(int64_t bid, int sub2, int64_t& tile,
 // (covers FP32 rounding of the box and of the per-pixel alpha test).
 constexpr float kCullMargin = 0.25f;
 
+// Whether the ellipse {d^T Q d <= S} around (mx, my) reaches the 8x8 pixel
+// centres [x0, x0 + 7] x [y0, y0 + 7] widened by kCullMargin: the minimum of
+// the quadratic over that rectangle (zero if it holds the centre, else on an
+// edge, where the quadratic in the free coordinate has its minimum clamped to
+// the edge) against S.  ia = 1/a, ic = 1/c (a, c > 0).
+__device__ __forceinline__ bool quad_reaches(float mx, float my, float a, float b, float c, float ia,
+                                             float ic, float S, float x0, float y0) {
+  const float lx = x0 - kCullMargin - mx, hx = x0 + 7.f + kCullMargin - mx;
+  const float ly = y0 - kCullMargin - my, hy = y0 + 7.f + kCullMargin - my;
+  if (lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f) return true;
+  float best = INFINITY;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float X = e ? hx : lx;  // edge x = const, free y
+    const float ty = fminf(fmaxf(-b * X * ic, ly), hy);
+    best = fminf(best, fmaf(a * X, X, fmaf(2.f * b * X, ty, c * ty * ty)));
+    const float Y = e ? hy : ly;  // edge y = const, free x
+    const float tx = fminf(fmaxf(-b * Y * ia, lx), hx);
+    best = fminf(best, fmaf(c * Y, Y, fmaf(2.f * b * Y, tx, a * tx * tx)));
+  }
+  return best <= S;
+}
+
 inline RasterParams make_params(int32_t nv, const gs_camera* cams, const gs_raster_cfg& cfg) {
   RasterParams p{};
   p.nv = nv;
