@@ -8,9 +8,9 @@
 //      depth bits (stable LSD radix sort, so equal depths keep index order;
 //      the first pass drops the +inf depths of splats without tiles and the
 //      top pass runs only for depth ranges wider than 8 binades),
-//   2. gathers the splats' tile rectangles in that order and sums their tile
-//      counts per block of 256 splats (one small scan gives every block's pair
-//      offset and the total K),
+//   2. sums the splats' tile counts per block of 256 splats in that order
+//      (their clipped rectangles travel through the sort packed in 32 bits;
+//      one small scan gives every block's pair offset and the total K),
 //   3. emits (tile, splat) pairs in depth order, one thread per pair, and
 //   4. stably sorts the pairs by tile id only (ceil(log2 T) bits),
 // which yields each tile's list in (depth, index) order while moving the
@@ -153,6 +153,59 @@ __global__ __launch_bounds__(kSmallThreads) void scan_small_kernel(T* __restrict
   }
   if (threadIdx.x == 0) *total = carry;
 }
+
+// ----------------------------------------------------------------------------
+// tile rectangles
+// ----------------------------------------------------------------------------
+// Tile rectangle clipped to the tile grid (so no tile id can leave it).
+__device__ __forceinline__ int4 clip_rect(int4 r, int32_t tiles_x, int32_t tiles_y) {
+  return make_int4(max(r.x, 0), max(r.y, 0), min(r.z, tiles_x), min(r.w, tiles_y));
+}
+
+__device__ __forceinline__ uint32_t rect_tiles(int4 r) {
+  return (uint32_t)(max(r.z - r.x, 0) * max(r.w - r.y, 0));
+}
+
+// View of splat record e: splats of view v are e in [v n, (v + 1) n).
+__device__ __forceinline__ int view_of(const ViewTiles& vt, uint32_t e) {
+  return vt.nv > 1 ? (int)(e / (uint32_t)vt.n) : 0;
+}
+
+// A clipped rectangle in 32 bits (x0: 10, y0: 10, width: 6, height: 6 bits)
+// travels with its splat through the depth sort, so that the pair count and
+// emission read it in depth order without a random 16-byte gather (which
+// costs a whole cache line per splat).  Rectangles that do not fit get the
+// escape code and are read from the projection's array instead.
+constexpr uint32_t kRectEscape = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t pack_rect(int4 r) {
+  const int w = max(r.z - r.x, 0), h = max(r.w - r.y, 0);
+  if (r.x > 1022 || r.y > 1023 || w > 63 || h > 63) return kRectEscape;  // x0 = 1023: escape only
+  return (uint32_t)r.x | ((uint32_t)r.y << 10) | ((uint32_t)w << 20) | ((uint32_t)h << 26);
+}
+
+__device__ __forceinline__ int4 unpack_rect(uint32_t c) {
+  const int x = (int)(c & 1023u), y = (int)((c >> 10) & 1023u);
+  return make_int4(x, y, x + (int)((c >> 20) & 63u), y + (int)(c >> 26));
+}
+
+// Clipped rectangle of splat record e from its packed code (or, escaped,
+// from the projection's rectangles).
+__device__ __forceinline__ int4 splat_rect(uint32_t code, uint32_t e, const int4* __restrict__ rect,
+                                           const ViewTiles& vt) {
+  if (code != kRectEscape) return unpack_rect(code);
+  const int v = view_of(vt, e);
+  return clip_rect(rect[e], vt.tiles_x[v], vt.tiles_y[v]);
+}
+
+// 32-bit payload a downsweep moves with each element (to == nullptr: none):
+// the packed rectangle, built from `rect` in the first depth pass (where
+// the value is the splat record's index) and read from `from` in later ones.
+struct Payload {
+  const uint32_t* from = nullptr;
+  const int4* rect = nullptr;
+  ViewTiles vt;
+  uint32_t* to = nullptr;
+};
 
 // ----------------------------------------------------------------------------
 // LSD radix sort pass on (uint32 key, uint32 value), BITS-bit digits (1..11)
@@ -371,7 +424,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in /* null: index */,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t m,
     const uint64_t* m_dev, int64_t cap, int shift, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ totals, int64_t nblocks, DepthKeys dk) {
+    const uint32_t* __restrict__ totals, int64_t nblocks, DepthKeys dk, Payload pl) {
   constexpr int R = 1 << BITS;
   if (pass_is_identity(dk, shift)) return;
   if (m_dev) m = eff_count(m_dev, cap);
@@ -491,6 +544,31 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     if (keys_out) keys_out[dst] = k;  // null: values only (no later pass reads the keys)
     vals_out[dst] = s_vals[i];
   }
+
+  // 5. the payload, through the value slots of LDS: same positions, same runs
+  if (pl.to) {
+    __syncthreads();  // step 4 has read s_vals
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      if (kept[r]) {
+        const int64_t e = seg + r * 64 + lane;
+        uint32_t py;
+        if (pl.from) {
+          py = pl.from[e];
+        } else {
+          const int v = view_of(pl.vt, val[r]);
+          py = pack_rect(clip_rect(pl.rect[e], pl.vt.tiles_x[v], pl.vt.tiles_y[v]));
+        }
+        const uint32_t d = ((key[r] - kbase) >> shift) & (R - 1);
+        s_vals[s_wh[wave][d] + rank[r]] = py;
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < count; i += kThreads) {
+      const uint32_t d = ((s_keys[i] - kbase) >> shift) & (R - 1);
+      pl.to[s_gbase[d] + (uint32_t)i - s_lstart[d]] = s_vals[i];
+    }
+  }
 }
 
 // A pass over m elements, or, with m_dev set, over the device-side count
@@ -499,7 +577,7 @@ template <int BITS>
 hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                            uint32_t* vout, int64_t m, const uint64_t* m_dev, int shift,
                            uint32_t* hist, uint32_t* totals, const DepthKeys& dk,
-                           hipStream_t stream) {
+                           const Payload& pl, hipStream_t stream) {
   const int64_t nb = std::max<int64_t>(ceil_div(m, kTile), 1);
   radix_upsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, m, m_dev, m, shift, hist,
                                                                      nb, dk);
@@ -509,20 +587,21 @@ hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* k
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   radix_downsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(
-      kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb, dk);
+      kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb, dk, pl);
   return hipGetLastError();
 }
 
 // One stable pass over `bits` (1..kMaxAnyDigitBits) bits starting at `shift`.
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       int64_t m, const uint64_t* m_dev, int shift, int bits, uint32_t* hist,
-                      uint32_t* totals, const DepthKeys& dk, hipStream_t stream) {
+                      uint32_t* totals, const DepthKeys& dk, const Payload& pl,
+                      hipStream_t stream) {
   switch (bits) {
 #define GS_RADIX_CASE(B)                                                                  \
   case B:                                                                                 \
     if (B <= kMaxAnyDigitBits)                                                            \
       return radix_pass_bits<(B <= kMaxAnyDigitBits ? B : 1)>(kin, vin, kout, vout, m, m_dev, \
-                                                           shift, hist, totals, dk, stream); \
+                                                           shift, hist, totals, dk, pl, stream); \
     break;
     GS_RADIX_CASE(1)
     GS_RADIX_CASE(2)
@@ -567,46 +646,30 @@ int depth_plan(int widths[8]) {
 // ----------------------------------------------------------------------------
 // binning kernels
 // ----------------------------------------------------------------------------
-// Tile rectangle clipped to the tile grid (so no tile id can leave it).
-__device__ __forceinline__ int4 clip_rect(int4 r, int32_t tiles_x, int32_t tiles_y) {
-  return make_int4(max(r.x, 0), max(r.y, 0), min(r.z, tiles_x), min(r.w, tiles_y));
-}
+constexpr int kEmit = 256;  // splats per count / emit block
 
-__device__ __forceinline__ uint32_t rect_tiles(int4 r) {
-  return (uint32_t)(max(r.z - r.x, 0) * max(r.w - r.y, 0));
-}
-
-constexpr int kEmit = 256;  // splats per gather / emit block
-
-// View of splat record e: splats of view v are e in [v n, (v + 1) n).
-__device__ __forceinline__ int view_of(const ViewTiles& vt, uint32_t e) {
-  return vt.nv > 1 ? (int)(e / (uint32_t)vt.n) : 0;
-}
-
-// Rectangles in depth order (clipped to their view's tile grid) and, per
-// block of kEmit splats, the sum of their tile counts.  The depth sort left
-// only the splats with a finite depth (kept[0] of them) in the order buffer
-// that its last pass wrote (dinfo[2]).
-__global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
-                                                            const uint32_t* __restrict__ order0,
-                                                            const uint32_t* __restrict__ order1,
-                                                            const uint32_t* __restrict__ dinfo,
-                                                            const uint64_t* kept,
-                                                            const int4* __restrict__ rect,
-                                                            ViewTiles vt,
-                                                            int4* __restrict__ srect,
-                                                            uint64_t* __restrict__ bsum) {
+// Per block of kEmit splats in depth order, the sum of their tile counts.
+// The depth sort left only the splats with a finite depth (kept[0] of them)
+// in the order and packed-rectangle buffers its last pass wrote (dinfo[2]).
+__global__ __launch_bounds__(kEmit) void pair_count_kernel(int64_t n,
+                                                           const uint32_t* __restrict__ order0,
+                                                           const uint32_t* __restrict__ order1,
+                                                           const uint32_t* __restrict__ prect0,
+                                                           const uint32_t* __restrict__ prect1,
+                                                           const uint32_t* __restrict__ dinfo,
+                                                           const uint64_t* kept,
+                                                           const int4* __restrict__ rect,
+                                                           ViewTiles vt,
+                                                           uint64_t* __restrict__ bsum) {
   __shared__ uint64_t s_w[kEmit / 64];
   const int64_t nk = eff_count(kept, n);
-  const uint32_t* __restrict__ order = dinfo[2] ? order1 : order0;
+  const bool second = dinfo[2] != 0u;
   const int64_t p = (int64_t)blockIdx.x * kEmit + threadIdx.x;
   uint64_t c = 0;
   if (p < nk) {
-    const uint32_t e = order[p];
-    const int v = view_of(vt, e);
-    const int4 r = clip_rect(rect[e], vt.tiles_x[v], vt.tiles_y[v]);
-    srect[p] = r;
-    c = rect_tiles(r);
+    const uint32_t code = (second ? prect1 : prect0)[p];
+    const uint32_t e = code == kRectEscape ? (second ? order1 : order0)[p] : 0u;
+    c = rect_tiles(splat_rect(code, e, rect, vt));
   }
   uint64_t excl;
   const uint64_t tot = block_exclusive_scan<uint64_t>(c, &excl, s_w);
@@ -622,9 +685,11 @@ __global__ __launch_bounds__(kEmit) void gather_rect_kernel(int64_t n,
 // (device-side count) nothing is written unless the total fits `cap`.
 __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* __restrict__ order0,
                                                      const uint32_t* __restrict__ order1,
+                                                     const uint32_t* __restrict__ prect0,
+                                                     const uint32_t* __restrict__ prect1,
                                                      const uint32_t* __restrict__ dinfo,
                                                      const uint64_t* kept,
-                                                     const int4* __restrict__ srect,
+                                                     const int4* __restrict__ rect,
                                                      const uint64_t* __restrict__ boff,
                                                      ViewTiles vt, const uint64_t* total,
                                                      int64_t cap, uint32_t* __restrict__ tkeys,
@@ -636,15 +701,18 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
   __shared__ uint32_t s_w[kEmit / 64];
   const int t = threadIdx.x;
   const int64_t nk = eff_count(kept, n);
-  const uint32_t* __restrict__ order = dinfo[2] ? order1 : order0;
+  const bool second = dinfo[2] != 0u;
+  const uint32_t* __restrict__ order = second ? order1 : order0;
+  const uint32_t* __restrict__ prect = second ? prect1 : prect0;
   const int64_t p0 = (int64_t)blockIdx.x * kEmit;
   const int64_t left = nk - p0;
   const int nb = left <= 0 ? 0 : (left < kEmit ? (int)left : kEmit);
   uint32_t c = 0;
   if (t < nb) {
-    const int4 r = srect[p0 + t];
+    const uint32_t gid = order[p0 + t];
+    const int4 r = splat_rect(prect[p0 + t], gid, rect, vt);
     s_rect[t] = r;
-    s_gid[t] = order[p0 + t];
+    s_gid[t] = gid;
     c = rect_tiles(r);
   }
   uint32_t excl;
@@ -774,7 +842,8 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles) {
   p.off_gval[0] = take(n4);
   p.off_gval[1] = take(n4);
   p.off_bsum = take(sizeof(uint64_t) * (size_t)ceil_div(n1, kEmit));
-  p.off_srect = take(sizeof(int32_t) * 4 * (size_t)n1);
+  p.off_prect[0] = take(n4);
+  p.off_prect[1] = take(n4);
   p.off_pkey[0] = take(c4);
   p.off_pkey[1] = take(c4);
   p.off_pval = take(c4);
@@ -841,21 +910,29 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     dk.low_mask = (1u << widths[0]) - 1u;
     dk.first = k == 0;
     dk.out_index = cur ^ 1;
+    // the packed rectangles travel in the same ping-pong order as the ids
+    Payload pl;
+    pl.from = k == 0 ? nullptr : u32(p.off_prect[cur]);
+    pl.rect = r4;
+    pl.vt = vt;
+    pl.to = u32(p.off_prect[cur ^ 1]);
     GS_TRY(radix_pass(kin, vin, u32(p.off_gkey[cur ^ 1]), u32(p.off_gval[cur ^ 1]), n,
-                      k == 0 ? nullptr : kept_count, shift, widths[k], hist, totals, dk, stream),
+                      k == 0 ? nullptr : kept_count, shift, widths[k], hist, totals, dk, pl,
+                      stream),
            "depth radix pass");
     shift += widths[k];
     cur ^= 1;
   }
   const uint32_t* order0 = u32(p.off_gval[0]);
   const uint32_t* order1 = u32(p.off_gval[1]);
+  const uint32_t* prect0 = u32(p.off_prect[0]);
+  const uint32_t* prect1 = u32(p.off_prect[1]);
 
-  // 2. rectangles in depth order, pair offsets per block of splats, total K
-  int4* srect = reinterpret_cast<int4*>(ws + p.off_srect);
+  // 2. tile counts in depth order, pair offsets per block of splats, total K
   const int64_t nbe = ceil_div(n, kEmit);
-  gather_rect_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, dinfo, kept_count, r4,
-                                                           vt, srect, bsum);
-  GS_TRY(hipGetLastError(), "gather_rect_kernel");
+  pair_count_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, prect0, prect1, dinfo,
+                                                          kept_count, r4, vt, bsum);
+  GS_TRY(hipGetLastError(), "pair_count_kernel");
   scan_small_kernel<uint64_t><<<1, kSmallThreads, 0, stream>>>(bsum, nbe, total);
   GS_TRY(hipGetLastError(), "pair offset scan");
   int64_t m = p.capacity;  // device-count mode: grids sized by the capacity
@@ -884,8 +961,9 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   vbuf[0] = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(sorted_ids) : u32(p.off_pval);
   vbuf[1] = (passes % 2 == 0) ? u32(p.off_pval) : reinterpret_cast<uint32_t*>(sorted_ids);
   uint32_t* kbuf[2] = {u32(p.off_pkey[0]), u32(p.off_pkey[1])};
-  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, dinfo, kept_count, srect,
-                                                   bsum, vt, m_dev, p.capacity, kbuf[0], vbuf[0]);
+  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, prect0, prect1, dinfo,
+                                                   kept_count, r4, bsum, vt, m_dev, p.capacity,
+                                                   kbuf[0], vbuf[0]);
   GS_TRY(hipGetLastError(), "emit_kernel");
 
   // 4. stable sort of the pairs by tile id
@@ -895,7 +973,7 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     // the keys of the last pass are only needed by tile_range_kernel
     uint32_t* kout = (k + 1 == passes && passes == 1) ? nullptr : kbuf[cur ^ 1];
     GS_TRY(radix_pass(kbuf[cur], vbuf[cur], kout, vbuf[cur ^ 1], m, m_dev, shift,
-                      widths[k], hist, totals, DepthKeys{}, stream),
+                      widths[k], hist, totals, DepthKeys{}, Payload{}, stream),
            "tile radix pass");
     shift += widths[k];
     cur ^= 1;

@@ -63,7 +63,7 @@ struct BinSortPlan {
   // workspace layout (byte offsets)
   size_t off_gkey[2], off_gval[2];  // depth keys / splat ids, ping-pong [n]
   size_t off_bsum;                  // tile-count sums per block of splats -> pair offsets
-  size_t off_srect;                 // clipped tile rectangles in depth order [n]
+  size_t off_prect[2];              // packed clipped tile rectangles, ping-pong with the ids [n]
   size_t off_pkey[2];               // pair tile keys, ping-pong [capacity]
   size_t off_pval;                  // pair ids, second buffer [capacity]
   size_t off_hist;                  // radix digit counts [2^digit bits * max blocks]

@@ -203,6 +203,38 @@ def test_bin_sort_depth_key_ranges(gs, oracle, kind):
     np.testing.assert_array_equal(ids, ref_ids)
 
 
+def test_bin_sort_wide_and_far_rectangles(gs, oracle):
+    """Rectangles wider or taller than 63 tiles and tiles beyond x = 1022
+    (a 1025-tile-wide grid), mixed with ordinary ones and culled splats."""
+    from paper_2503_14171_amd import scenes
+    rng = np.random.default_rng(77)
+    n = 20000
+    cam = scenes.make_camera(8200, 600)
+    cfg = scenes.render_config(0, tile_size=8)
+    tx, ty = _tiles_xy(cam, 8)
+    assert tx == 1025
+    x0 = rng.integers(0, tx, n)
+    y0 = rng.integers(0, ty, n)
+    w = rng.integers(1, 4, n)
+    h = rng.integers(1, 4, n)
+    wide = rng.random(n) < 0.03
+    w[wide] = rng.integers(60, 130, wide.sum())
+    tall = rng.random(n) < 0.03
+    h[tall] = rng.integers(60, 75, tall.sum())
+    far = rng.random(n) < 0.1
+    x0[far] = rng.integers(1015, tx, far.sum())
+    rect = np.stack([x0, y0, np.minimum(x0 + w, tx), np.minimum(y0 + h, ty)], 1).astype(np.int32)
+    d32 = rng.uniform(0.5, 30.0, n).astype(np.float32)
+    culled = rng.random(n) < 0.2
+    d32[culled] = np.inf
+    rect[culled] = 0
+    print("bin_sort wide and far rectangles", flush=True)
+    ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
+    ref_ids, ref_ranges = oracle.tile_lists(d32, rect, tx, ty)
+    np.testing.assert_array_equal(ranges, ref_ranges)
+    np.testing.assert_array_equal(ids, ref_ids)
+
+
 def test_bin_sort_capacity_error_and_empty(gs, oracle):
     import torch
     from paper_2503_14171_amd import scenes
