@@ -646,7 +646,10 @@ int depth_plan(int widths[8]) {
 // ----------------------------------------------------------------------------
 // binning kernels
 // ----------------------------------------------------------------------------
-constexpr int kEmit = 256;  // splats per count / emit block
+#ifndef GSUP_EMIT_BLOCK
+#define GSUP_EMIT_BLOCK 256
+#endif
+constexpr int kEmit = GSUP_EMIT_BLOCK;  // splats per count / emit block
 
 // Per block of kEmit splats in depth order, the sum of their tile counts.
 // The depth sort left only the splats with a finite depth (kept[0] of them)
@@ -672,7 +675,7 @@ __global__ __launch_bounds__(kEmit) void pair_count_kernel(int64_t n,
     c = rect_tiles(splat_rect(code, e, rect, vt));
   }
   uint64_t excl;
-  const uint64_t tot = block_exclusive_scan<uint64_t>(c, &excl, s_w);
+  const uint64_t tot = block_exclusive_scan<uint64_t, kEmit>(c, &excl, s_w);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
@@ -716,7 +719,7 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
     c = rect_tiles(r);
   }
   uint32_t excl;
-  const uint32_t tot = block_exclusive_scan<uint32_t>(c, &excl, s_w);
+  const uint32_t tot = block_exclusive_scan<uint32_t, kEmit>(c, &excl, s_w);
   s_off[t] = excl;
   if (t == 0) s_off[nb] = tot;
   __syncthreads();
