@@ -53,6 +53,15 @@ __device__ __forceinline__ void axis_map(int X, int n_lo, int n_hi, int& cell, f
   t = (float)(num - i * den) / (float)den;
 }
 
+// Local coordinate of output index X inside cell `cell` (the cell axis_map
+// gives X); no division by the cell count: the adjoint loops over the output
+// indices of known cells.
+__device__ __forceinline__ float local_coord(int X, int n_lo, int n_hi, int cell) {
+  const int64_t den = 2 * (int64_t)n_hi;
+  const int64_t r = (int64_t)(2 * X + 1) * n_lo - n_hi - (int64_t)cell * den;
+  return (float)r / (float)den;
+}
+
 // V (values) and D (y-derivatives) of low-res row r along x at the lane's column.
 __device__ __forceinline__ void row_terms(const float* __restrict__ in, int w, int r, int i, float h0,
                                           float h1, float h2, float h3, float (&V)[3],
@@ -172,15 +181,17 @@ __global__ __launch_bounds__(kThreads) void upscale_bwd_kernel(UpParams p,
   float acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0.f;
-  // the node is corner 1 (right / bottom) of cell i-1 and corner 0 of cell i
+  // the node is corner 1 (right / bottom) of cell i-1 and corner 0 of cell i;
+  // output columns of those two cells (the same for every output row)
+  int xs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) xs[k] = cell_start(i - 1 + k, w, W);
   for (int cy = j - 1; cy <= j; ++cy) {
     if (cy < 0 || cy > h - 2) continue;
     const int ry = cy == j ? 0 : 1;
     const int Y0 = cell_start(cy, h, H), Y1 = cell_start(cy + 1, h, H);
     for (int Y = Y0; Y < Y1; ++Y) {
-      int jj;
-      float ty;
-      axis_map(Y, h, H, jj, ty);
+      const float ty = local_coord(Y, h, H, cy);  // Y lies in cell cy
       float hy0, hy1, hy2, hy3;
       hermite(ty, hy0, hy1, hy2, hy3);
       const float wyV = ry ? hy1 : hy0, wyD = ry ? hy3 : hy2;
@@ -188,11 +199,9 @@ __global__ __launch_bounds__(kThreads) void upscale_bwd_kernel(UpParams p,
       for (int cx = i - 1; cx <= i; ++cx) {
         if (cx < 0 || cx > w - 2) continue;
         const int rx = cx == i ? 0 : 1;
-        const int X0 = cell_start(cx, w, W), X1 = cell_start(cx + 1, w, W);
+        const int X0 = xs[cx - i + 1], X1 = xs[cx - i + 2];
         for (int X = X0; X < X1; ++X) {
-          int ii;
-          float tx;
-          axis_map(X, w, W, ii, tx);
+          const float tx = local_coord(X, w, W, cx);  // X lies in cell cx
           float hx0, hx1, hx2, hx3;
           hermite(tx, hx0, hx1, hx2, hx3);
           const float wxV = rx ? hx1 : hx0, wxD = rx ? hx3 : hx2;
