@@ -46,7 +46,10 @@ using namespace raster_detail;
 namespace {
 
 
-template <int TILE, bool GRAD, int BATCH, int SUB>
+// AUX: the per-pixel blend count and walk end are kept (n_blend or state
+// requested); the headline frame needs neither and saves two updates per
+// blended fragment.
+template <int TILE, bool GRAD, int BATCH, int SUB, bool AUX>
 __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
                                                             const gs_splat* __restrict__ splats,
                                                             const int32_t* __restrict__ ids,
@@ -190,8 +193,10 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
             B1 = fmaf(gc.x, w, B1);
             B2 = fmaf(gc.y, w, B2);
             T -= w;
-            ++nb;
-            lastpos = base + j + 1;
+            if (AUX) {
+              ++nb;
+              lastpos = base + j + 1;
+            }
             done = T < p.t_min;
           }
         }
@@ -215,8 +220,8 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
     o[1] = fmaf(T, p.bg[1], B1);
     o[2] = fmaf(T, p.bg[2], B2);
   }
-  if (n_blend) n_blend[pix] = nb;
-  if (state) {  // for the backward pass: final T and derivatives, end of the walked list
+  if (AUX && n_blend) n_blend[pix] = nb;
+  if (AUX && state) {  // for the backward pass: final T and derivatives, end of the walked list
     state[pix] = make_float4(T, Tx, Ty, Txy);
     last[pix] = lastpos;
   }
@@ -232,9 +237,13 @@ struct RasterOut {
 template <int TILE, bool GRAD, int BATCH, int SUB>
 void launch(const RasterParams& p, const gs_splat* splats, const int32_t* ids, const int2* ranges,
             const RasterOut& o, hipStream_t stream) {
-  const int64_t grid = tile_grid(p.tiles, SUB * SUB);
-  raster_kernel<TILE, GRAD, BATCH, SUB><<<(unsigned)grid, TILE * TILE, 0, stream>>>(
-      p, splats, ids, ranges, o.out, o.n_blend, o.state, o.last);
+  const unsigned grid = (unsigned)tile_grid(p.tiles, SUB * SUB);
+  if (o.n_blend || o.state)
+    raster_kernel<TILE, GRAD, BATCH, SUB, true><<<grid, TILE * TILE, 0, stream>>>(
+        p, splats, ids, ranges, o.out, o.n_blend, o.state, o.last);
+  else
+    raster_kernel<TILE, GRAD, BATCH, SUB, false><<<grid, TILE * TILE, 0, stream>>>(
+        p, splats, ids, ranges, o.out, o.n_blend, o.state, o.last);
 }
 
 // List tiles of edge TILE * SUB, workgroups of TILE x TILE pixels.  batch
