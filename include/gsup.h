@@ -57,7 +57,7 @@ typedef enum gs_status {
   GS_ERR_INVALID_ARGUMENT = 1, /* a pointer, size or setting is out of range */
   GS_ERR_CAPACITY = 2,         /* gs_bin_sort: more (tile, splat) pairs than `capacity` */
   GS_ERR_HIP = 3,              /* the HIP runtime reported an error */
-  GS_ERR_UNSUPPORTED = 4       /* a setting this build does not implement */
+  GS_ERR_UNSUPPORTED = 4       /* a setting the library does not implement */
 } gs_status;
 
 /* Pinhole camera.  A world point p maps to camera space t = R p + t_W with

@@ -147,7 +147,7 @@ def test_bin_sort_stable_under_depth_ties(gs, oracle, seed):
 
 
 _DEPTH_KINDS = ["full_range", "narrow", "eight_binades", "just_over_eight_binades", "mostly_culled",
-                "one_kept", "all_equal", "denormal_and_huge"]
+                "one_kept", "all_culled", "all_equal", "denormal_and_huge"]
 
 
 def _depth_set(kind, rng, n):
@@ -171,6 +171,8 @@ def _depth_set(kind, rng, n):
         d = np.full(n, np.inf, f32)
         d[n // 3] = f32(4.0)
         return d
+    if kind == "all_culled":
+        return np.full(n, np.inf, f32)
     if kind == "all_equal":
         return np.full(n, 2.5, f32)
     if kind == "denormal_and_huge":
