@@ -432,3 +432,55 @@ def test_fd_bicubic_chain(gs, oracle, tiny_lowres):
         torch.cuda.synchronize()
         ref = oracle.upscale(ref_slopes, W, H)
         np.testing.assert_allclose(out.cpu().numpy(), ref, atol=5e-6, rtol=0)
+
+
+def test_bin_sort_views_matches_per_view_lexsort(gs, oracle):
+    """Two views of different tile grids sorted together (one with tiles beyond
+    x = 1022 and over-wide rectangles, i.e. escaped packed rectangles), with
+    culled splats: view after view, each view's lists must equal a
+    lexicographic sort of that view's records."""
+    import torch
+    from paper_2503_14171_amd import scenes
+    rng = np.random.default_rng(91)
+    n = 12000
+    cams = [scenes.make_camera(8200, 160), scenes.make_camera(300, 200)]
+    cfg = scenes.render_config(0, tile_size=8)
+    depth, rect, refs = [], [], []
+    for cam in cams:
+        tx, ty = _tiles_xy(cam, 8)
+        x0 = rng.integers(0, tx, n)
+        y0 = rng.integers(0, ty, n)
+        w = rng.integers(1, 4, n)
+        wide = rng.random(n) < 0.05
+        w[wide] = rng.integers(60, 100, wide.sum())
+        h = rng.integers(1, 3, n)
+        r = np.stack([x0, y0, np.minimum(x0 + w, tx), np.minimum(y0 + h, ty)], 1).astype(np.int32)
+        d = rng.uniform(0.5, 30.0, n).astype(np.float32)
+        culled = rng.random(n) < 0.25
+        d[culled] = np.inf
+        r[culled] = 0
+        depth.append(d)
+        rect.append(r)
+        refs.append(oracle.tile_lists(d, r, tx, ty))
+    K = sum(int(ids.shape[0]) for ids, _ in refs)
+    tiles = gs.gs_num_tiles_views(cams, 8)
+    ws = torch.empty(gs.gs_bin_sort_views_workspace_size(n, cams, cfg, K), dtype=torch.uint8, device="cuda")
+    ids = torch.full((K,), -7, dtype=torch.int32, device="cuda")
+    ranges = torch.full((tiles, 2), -7, dtype=torch.int32, device="cuda")
+    kdev = torch.zeros(1, dtype=torch.int64, device="cuda")
+    print("bin_sort views with escaped rectangles", flush=True)
+    gs.gs_bin_sort_views(n, cams, cfg, _dev(np.concatenate(depth)), _dev(np.concatenate(rect)), K, ids,
+                         ranges, kdev, ws)
+    torch.cuda.synchronize()
+    assert int(kdev.item()) == K
+    got_ids, got_ranges = ids.cpu().numpy(), ranges.cpu().numpy()
+    pos, toff = 0, 0
+    for v, (ref_ids, ref_ranges) in enumerate(refs):
+        k = ref_ids.shape[0]
+        np.testing.assert_array_equal(got_ids[pos:pos + k], ref_ids + v * n)
+        t = ref_ranges.shape[0]
+        want = np.where(ref_ranges[:, 1:2] > ref_ranges[:, 0:1], ref_ranges + pos, 0)
+        np.testing.assert_array_equal(got_ranges[toff:toff + t], want)
+        pos += k
+        toff += t
+    assert toff == tiles
