@@ -40,8 +40,8 @@ class Renderer:
             self._bufs[key] = b
         return b
 
-    def _ensure_capacity(self, b: dict, cam: dict, cfg: dict, capacity: int):
-        if capacity <= b["capacity"]:
+    def _ensure_capacity(self, b: dict, cam: dict, cfg: dict, capacity: int, shrink: bool = False):
+        if capacity <= b["capacity"] and not shrink:
             return
         capacity = int(capacity)
         b["ids"] = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
@@ -60,6 +60,7 @@ class Renderer:
         b = b or self._view_bufs(cam, cfg)
         if b["capacity"] == 0:
             self._ensure_capacity(b, cam, cfg, 4 * self.n + 1024)
+        self._apply_shrink(b, cam, cfg)
         try:
             k = L.gs_bin_sort(self.n, b["depth"], b["rect"], cam, cfg, b["capacity"], b["ids"],
                               b["ranges"], b["workspace"])
@@ -70,7 +71,17 @@ class Renderer:
             k = L.gs_bin_sort(self.n, b["depth"], b["rect"], cam, cfg, b["capacity"], b["ids"],
                               b["ranges"], b["workspace"])
         b["n_pairs"] = k
+        # the pair passes size their grids by the capacity: bring it near the
+        # count (25 % headroom) before the next sort, not now (b["ids"] holds
+        # this sort's lists); pairs_fit grows it again when a frame overflows
+        if b["capacity"] > 2 * k + 4096:
+            b["shrink_to"] = int(k * 1.25) + 1024
         return k
+
+    def _apply_shrink(self, b: dict, cam: dict, cfg: dict):
+        cap = b.pop("shrink_to", None)
+        if cap is not None and cap < b["capacity"]:
+            self._ensure_capacity(b, cam, cfg, cap, shrink=True)
 
     def bin_sort_async(self, cam: dict, cfg: dict, b: dict | None = None) -> None:
         """gs_bin_sort_async: no wait; the pair count lands in b["n_pairs_dev"].
@@ -79,6 +90,7 @@ class Renderer:
         b = b or self._view_bufs(cam, cfg)
         if b["capacity"] == 0:
             self._ensure_capacity(b, cam, cfg, 4 * self.n + 1024)
+        self._apply_shrink(b, cam, cfg)
         if "n_pairs_dev" not in b:
             b["n_pairs_dev"] = torch.zeros(1, dtype=torch.int64, device=self.device)
         L.gs_bin_sort_async(self.n, b["depth"], b["rect"], cam, cfg, b["capacity"], b["ids"],
@@ -91,6 +103,8 @@ class Renderer:
         k = int(b["n_pairs_dev"].item())
         b["n_pairs"] = k
         if k <= b["capacity"]:
+            if b["capacity"] > 2 * k + 4096:
+                b["shrink_to"] = int(k * 1.25) + 1024  # applied before the next sort
             return True
         if k >= 2 ** 31:
             raise L.GsError(L.GS_ERR_CAPACITY, f"{k} pairs exceed the 2^31 index limit", k)
