@@ -45,6 +45,7 @@ class ViewBatch:
         self.up = torch.empty((sum(self.hi_px), 3), dtype=torch.float32, device=dev)
         self.n_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
         self.capacity = 0
+        self._shrink_to = 0
         self._alloc(capacity if capacity is not None else 4 * V * renderer.n + 1024)
         self.graph = None
 
@@ -83,6 +84,12 @@ class ViewBatch:
 
     def launch(self):
         """One frame: graph replay if captured, else the eager chain."""
+        if self._shrink_to:
+            self._alloc(self._shrink_to)
+            self._shrink_to = 0
+            if self.graph is not None:
+                self.graph = None
+                self.capture()
         if self.graph is not None:
             self.graph.replay()
         else:
@@ -90,9 +97,14 @@ class ViewBatch:
 
     def pairs_fit(self) -> bool:
         """Waits for the stream; False (and bigger buffers, graph dropped) if
-        the last frame's pairs did not fit."""
+        the last frame's pairs did not fit.  A capacity far above the count
+        is brought down to it plus 25 % before the next frame (the pair
+        passes size their grids by the capacity); a captured graph is
+        captured again either way."""
         k = int(self.n_pairs.item())
         if k <= self.capacity:
+            if self.capacity > 2 * k + 4096:
+                self._shrink_to = int(k * 1.25) + 1024  # before the next frame: ids stay readable
             return True
         if k >= 2 ** 31:
             raise L.GsError(L.GS_ERR_CAPACITY, f"{k} pairs exceed the 2^31 index limit", k)
