@@ -40,6 +40,7 @@ class TrainViews:
         self.d_splats = torch.empty((V * n1, 9), dtype=f, device=device)
         self.n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
         self.capacity = 0
+        self._shrink_to = 0
         self._alloc(4 * V * self.n + 1024)
 
     def _alloc(self, capacity: int):
@@ -51,12 +52,19 @@ class TrainViews:
     def forward(self, means, log_scales, quats, opacity, sh) -> torch.Tensor:
         """Upscaled images of all views back to back, [sum W*H, 3]."""
         args = (means, log_scales, quats, opacity, sh)
+        if self._shrink_to:  # the last step's lists are no longer needed
+            self._alloc(self._shrink_to)
+            self._shrink_to = 0
         while True:
             L.gs_project_views(*args, self.cams, self.cfg, self.splats, self.depth, self.rect)
             L.gs_bin_sort_views(self.n, self.cams, self.cfg, self.depth, self.rect, self.capacity, self.ids,
                                 self.ranges, self.n_pairs, self.workspace)
             k = int(self.n_pairs.item())
             if k <= self.capacity:
+                # the pair passes size their grids by the capacity: keep it
+                # near the count from the next step on
+                if self.capacity > 2 * k + 4096:
+                    self._shrink_to = int(k * 1.25) + 1024
                 break
             if k >= 2 ** 31:
                 raise L.GsError(L.GS_ERR_CAPACITY, f"{k} pairs exceed the 2^31 index limit", k)
