@@ -5,15 +5,18 @@ scene whose inputs already sit in HBM: gs_project -> gs_bin_sort ->
 gs_raster_grad (colour + dI/dx, dI/dy, d2I/dxdy) -> gs_upscale_hermite.
 The default workload is the 3M-Gaussian scene (SH degree 3) rendered at
 960x540 and upscaled x4 to 3840x2160.  Throughput is high-res output
-megapixels per second.
+megapixels per second with two frames in flight (--inflight), each on a
+stream and a set of buffers of its own; the same frames one at a time give
+the per-frame latency, reported beside it.
 
-Beside it the script measures, on the same GPU, the direct full-resolution
-render (gs_project + gs_bin_sort + plain gs_raster_grad at 3840x2160), the
-PSNR of the upscaled image against it, per-kernel HIP-event times, the
+Beside it the script measures, on the same GPU and with the same number of
+frames in flight, the direct full-resolution render (gs_project +
+gs_bin_sort + plain gs_raster_grad at 3840x2160), the PSNR of the upscaled
+image against it, per-stage HIP-event times on each frame's stream, the
 raster kernel's arithmetic roofline and the upscaler's HBM roofline, and the
 FP64 CPU oracle on a bounded sample of the same frame (rank 0, N = 1).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene_x4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene_x4] [--inflight 2]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -83,7 +86,7 @@ def run_gpu(args):
     import torch
 
     from paper_2503_14171_amd import scenes
-    from paper_2503_14171_amd.render import Renderer
+    from paper_2503_14171_amd.render import FramePipeline, Renderer
 
     name, sx, sy = WORKLOADS[args.workload]
     sc = scenes.workload_scene(name)
@@ -95,49 +98,75 @@ def run_gpu(args):
     cam_hi = scenes.scale_camera(cam, W, H)
     torch.cuda.set_device(0)
     rd = Renderer(sc)
+    depth = args.inflight
 
     # Rotating output sets (> 512 MB in total) so that the 256 MB MALL does
-    # not absorb the upscaler's reads and writes between steps.
+    # not absorb the upscaler's reads and writes between steps; slot i of the
+    # pipeline only ever uses sets i, i + depth, i + 2 depth, ...
     set_bytes = (w * h * 12 + W * H * 3) * 4
-    nsets = max(2, math.ceil(640e6 / set_bytes))
+    per_slot = math.ceil(max(2, math.ceil(640e6 / set_bytes)) / depth)
+    nsets = per_slot * depth
     lows = [torch.empty((h, w, 12), dtype=torch.float32, device="cuda") for _ in range(nsets)]
     ups = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(nsets)]
 
-    def step(k, ev=None):
-        lo, up = lows[k % nsets], ups[k % nsets]
-        if ev:
-            ev[0].record()
-        b = rd.project(cam, cfg)
-        if ev:
-            ev[1].record()
-        rd.bin_sort_async(cam, cfg, b)
-        if ev:
-            ev[2].record()
-        rd.raster(cam, cfg, True, lo, b=b)
-        if ev:
-            ev[3].record()
-        rd.upscale(lo, W, H, up)
-        if ev:
-            ev[4].record()
+    def frames(d, steps, warmup, with_events):
+        """Times `steps` upscaled frames with `d` in flight; per-stage events
+        on each frame's own stream."""
+        pipe = FramePipeline(rd, d)
+        used = [0] * d
+        last = [0]
 
-    # the pair count stays on the device: run until a frame fits the buffers
-    step(0)
-    while not rd.pairs_fit(cam, cfg):
-        step(0)
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    evs = [_events(torch, 5) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(args.warmup + k, evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = 1e3 * wall / args.steps
-    assert rd.pairs_fit(cam, cfg), "pair count changed during the timed frames"
-    stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])
-    st_ms = stage.mean(0)
+        def step(ev=None):
+            i = pipe.next_slot
+            j = i + d * (used[i] % (nsets // d))
+            used[i] += 1
+            last[0] = j
+            lo, up = lows[j], ups[j]
+
+            def frame(r):
+                if ev:
+                    ev[0].record()
+                b = r.project(cam, cfg)
+                if ev:
+                    ev[1].record()
+                r.bin_sort_async(cam, cfg, b)
+                if ev:
+                    ev[2].record()
+                r.raster(cam, cfg, True, lo, b=b)
+                if ev:
+                    ev[3].record()
+                r.upscale(lo, W, H, up)
+                if ev:
+                    ev[4].record()
+            pipe.submit(frame)
+
+        # pair counts stay on the device: run until every slot's frame fits
+        # its buffers, then once more so that capacity changes have landed
+        while True:
+            for _ in range(d):
+                step()
+            if pipe.pairs_fit(cam, cfg):
+                break
+        for _ in range(d + warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [_events(torch, 5) for _ in range(steps)] if with_events else [None] * steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        assert pipe.pairs_fit(cam, cfg), "pair count changed during the timed frames"
+        st = None
+        if with_events:
+            st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs]).mean(0)
+        return ms, st, last[0]
+
+    ms_step, st_ms, last_set = frames(depth, args.steps, args.warmup, True)
+    # one frame at a time: the latency of a frame, and the stages with the GPU
+    # to themselves
+    ms_serial, st_serial = frames(1, args.steps, args.warmup, True)[:2] if depth > 1 else (ms_step, st_ms)
     # the upscaler's own launch duration: back-to-back launches over the
     # rotating buffer sets between two events on the launch stream
     ue = _events(torch, 2)
@@ -150,30 +179,38 @@ def run_gpu(args):
     up_launch_ms = ue[0].elapsed_time(ue[1]) / nup
 
     # direct full-resolution render (plain compositing) on the same GPU, with
-    # the frame's own tile size and with the other tile sizes; the best one
-    # is the baseline the speed-up is quoted against
-    direct_out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    # the same number of frames in flight, at the frame's own tile size and at
+    # the other tile sizes; the best one is the baseline the speed-up is
+    # quoted against
+    direct_outs = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(depth)]
 
-    def time_direct(tile):
+    def time_direct(tile, d):
         cfg_d = dict(cfg, tile_size=tile)
+        pipe = FramePipeline(rd, d)
 
         def direct_step(ev=None):
-            if ev:
-                ev[0].record()
-            b = rd.project(cam_hi, cfg_d)
-            if ev:
-                ev[1].record()
-            rd.bin_sort_async(cam_hi, cfg_d, b)
-            if ev:
-                ev[2].record()
-            rd.raster(cam_hi, cfg_d, False, direct_out, b=b)
-            if ev:
-                ev[3].record()
+            out = direct_outs[pipe.next_slot]
 
-        direct_step()
-        while not rd.pairs_fit(cam_hi, cfg_d):
-            direct_step()
-        for _ in range(max(1, args.warmup)):
+            def frame(r):
+                if ev:
+                    ev[0].record()
+                b = r.project(cam_hi, cfg_d)
+                if ev:
+                    ev[1].record()
+                r.bin_sort_async(cam_hi, cfg_d, b)
+                if ev:
+                    ev[2].record()
+                r.raster(cam_hi, cfg_d, False, out, b=b)
+                if ev:
+                    ev[3].record()
+            pipe.submit(frame)
+
+        while True:
+            for _ in range(d):
+                direct_step()
+            if pipe.pairs_fit(cam_hi, cfg_d):
+                break
+        for _ in range(d + max(1, args.warmup)):
             direct_step()
         torch.cuda.synchronize()
         devs = [_events(torch, 4) for _ in range(args.steps)]
@@ -182,21 +219,27 @@ def run_gpu(args):
             direct_step(devs[k])
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / args.steps
-        assert rd.pairs_fit(cam_hi, cfg_d)
+        assert pipe.pairs_fit(cam_hi, cfg_d)
         st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in devs]).mean(0)
-        rd._bufs.pop((W, H, tile), None)  # free this tile size's buffers
+        if tile != cfg["tile_size"]:
+            pipe.drop_view(cam_hi, cfg_d)  # free this tile size's buffers
+        else:
+            for r in pipe.slots[1:]:
+                r._bufs.clear()
         return ms, st
 
     direct_all = {}
     for tile in sorted({args.tile, 16, 32, 64}):
-        direct_all[tile] = time_direct(tile)
+        direct_all[tile] = time_direct(tile, depth)
     best_tile = min(direct_all, key=lambda t: direct_all[t][0])
     ms_direct, dstage = direct_all[args.tile]
+    ms_direct_serial = time_direct(args.tile, 1)[0] if depth > 1 else ms_direct
     torch.cuda.synchronize()
+    direct_out = direct_outs[0]
     rd.render(cam_hi, cfg, False, direct_out)  # the reference image for PSNR
 
     # quality of the upscaled frame against the direct render
-    up = ups[(args.warmup + args.steps - 1) % nsets].clamp(0, 1)
+    up = ups[last_set].clamp(0, 1)
     ref = direct_out.clamp(0, 1)
     psnr = _psnr(up, ref)
 
@@ -204,7 +247,7 @@ def run_gpu(args):
     # difference slopes through the same Hermite kernel = Catmull-Rom) and
     # torch's bicubic (Keys a = -3/4); quality only, plus the slope kernel's time
     from paper_2503_14171_amd import _lib
-    lo_last = lows[(args.warmup + args.steps - 1) % nsets]
+    lo_last = lows[last_set]
     rgb_lo = lo_last[..., :3].contiguous()
     fd_in = torch.empty((h, w, 12), dtype=torch.float32, device="cuda")
     fd_up = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
@@ -241,6 +284,7 @@ def run_gpu(args):
 
     ras_ms = st_ms[2]
     achieved = frags * FLOP_PER_BLEND[True] / (ras_ms * 1e-3) / 1e12
+    achieved_serial = frags * FLOP_PER_BLEND[True] / (st_serial[2] * 1e-3) / 1e12
     up_bytes = w * h * UPSCALE_BYTES_LO + W * H * UPSCALE_BYTES_HI
     up_gbs = up_bytes / (st_ms[3] * 1e-3) / 1e9
     up_gbs_launch = up_bytes / (up_launch_ms * 1e-3) / 1e9
@@ -252,6 +296,9 @@ def run_gpu(args):
     return dict(best_direct=best, comparators=comparators,
         name=name, s=s, w=w, h=h, W=W, H=H, n=rd.n, cfg=cfg, value=value, ms_step=ms_step,
         stages_ms=dict(project=st_ms[0], bin_sort=st_ms[1], raster_grad=st_ms[2], upscale=st_ms[3]),
+        inflight=depth, ms_serial=ms_serial, ms_direct_serial=ms_direct_serial,
+        stages_serial=dict(project=st_serial[0], bin_sort=st_serial[1], raster_grad=st_serial[2],
+                           upscale=st_serial[3]), achieved_serial=achieved_serial,
         direct=dict(value=direct_value, ms_per_frame=ms_direct,
                     stages_ms=dict(project=dstage[0], bin_sort=dstage[1], raster_plain=dstage[2]),
                     pairs=pairs_hi, blended_fragments=frags_hi),
@@ -528,6 +575,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scene_x4", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="frames in flight on streams of their own (upscaled and direct paths alike)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle compositing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -571,7 +620,7 @@ def main():
         "config": {"workload": f"{name}: {res['n']} Gaussians, SH degree {res['cfg']['sh_degree']}, "
                                f"{w}x{h} rendered with gradients, upscaled x{s} to {W}x{H}",
                    "gaussians": res["n"], "lowres": [w, h], "highres": [W, H], "scale": s,
-                   "tile": args.tile},
+                   "tile": args.tile, "frames_in_flight": res["inflight"]},
         "roofline": {"kernel": "gs_raster_grad", "bound": "alu",
                      "achieved": round(res["achieved_tflops"], 3), "peak": FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(res["achieved_tflops"] / FP32_VALU_TFLOPS, 4),
@@ -589,6 +638,13 @@ def main():
                    "ms_per_frame": round(res["direct"]["ms_per_frame"], 4),
                    "stages_ms": {k: round(v, 4) for k, v in res["direct"]["stages_ms"].items()}},
         "speedup_vs_direct": round(res["value"] / res["direct"]["value"], 3),
+        "one_in_flight": {"ms_per_frame": round(res["ms_serial"], 4),
+                          "value": round(W * H / (res["ms_serial"] * 1e-3) / 1e6, 2),
+                          "stages_ms": {k: round(v, 4) for k, v in res["stages_serial"].items()},
+                          "raster_achieved": round(res["achieved_serial"], 3),
+                          "raster_frac": round(res["achieved_serial"] / FP32_VALU_TFLOPS, 4),
+                          "direct_ms_per_frame": round(res["ms_direct_serial"], 4),
+                          "speedup_vs_direct": round(res["ms_direct_serial"] / res["ms_serial"], 3)},
         "direct_best": {"tile": res["best_direct"]["tile"], "value": round(res["best_direct"]["value"], 2),
                         "ms_per_frame": round(res["best_direct"]["ms_per_frame"], 4),
                         "ms_by_tile": res["best_direct"]["by_tile"]},

@@ -3,7 +3,8 @@
 :class:`Renderer` keeps one scene's parameters and the per-view buffers in
 device memory and chains the four entry points on the current stream.  It
 only allocates buffers and forwards them; every step runs in libgsup's HIP
-kernels.
+kernels.  :class:`FramePipeline` keeps several frames in flight, each on a
+stream and a set of buffers of its own.
 """
 from __future__ import annotations
 
@@ -23,6 +24,14 @@ class Renderer:
         self.sh_degree = int(scene.get("sh_degree", round(self.sh.shape[1] ** 0.5) - 1))
         self.device = device
         self._bufs: dict = {}
+
+    def sibling(self) -> "Renderer":
+        """A renderer over the same scene tensors (shared, read only) with
+        per-view buffers of its own, for a frame in flight beside this one's."""
+        r = Renderer.__new__(Renderer)
+        r.__dict__.update(self.__dict__)
+        r._bufs = {}
+        return r
 
     # -- buffers -------------------------------------------------------------
     def _view_bufs(self, cam: dict, cfg: dict):
@@ -135,3 +144,73 @@ class Renderer:
     def render_upscaled(self, cam: dict, cfg: dict, W: int, H: int, lowres=None, out=None):
         low = self.render(cam, cfg, True, lowres)
         return self.upscale(low, W, H, out), low
+
+
+class FramePipeline:
+    """Frames in flight on streams of their own.
+
+    One frame is a chain of dependent launches (projection, the depth and tile
+    sort passes with their scans, the pair emission, the raster, the
+    upscale), and several of them launch far fewer workgroups than the chip
+    holds or wait on a single-block scan, so a lone frame leaves compute units
+    idle under and between them.  Slot i renders on stream i with a renderer
+    of its own (pair lists, workspace and counters; the scene tensors are
+    shared), so the next frame's projection and sort fill what this frame's
+    raster and scans leave.
+
+    :meth:`submit` makes the slot's stream wait for the caller's current
+    stream first, so inputs written there are seen; :meth:`join` makes the
+    caller's stream wait for every slot.  Frames in flight at the same time
+    need distinct output buffers, and a buffer a slot writes may be freed or
+    reused on another stream only after :meth:`join`.
+    """
+
+    def __init__(self, renderer: Renderer, depth: int = 2):
+        if depth < 1:
+            raise ValueError("a pipeline needs at least one slot")
+        self.slots = [renderer] + [renderer.sibling() for _ in range(depth - 1)]
+        dev = torch.device(renderer.device)
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(depth)]  # default priority
+        self._next = 0
+
+    @property
+    def depth(self) -> int:
+        return len(self.slots)
+
+    @property
+    def next_slot(self) -> int:
+        """The slot the next submit() runs on (to pick its output buffers)."""
+        return self._next
+
+    def submit(self, frame) -> int:
+        """Call ``frame(renderer)`` with the next slot's stream current (its
+        launches go there); returns the slot index."""
+        i = self._next
+        self._next = (i + 1) % len(self.slots)
+        s = self.streams[i]
+        s.wait_stream(torch.cuda.current_stream(s.device))
+        with torch.cuda.stream(s):
+            frame(self.slots[i])
+        return i
+
+    def join(self) -> None:
+        cur = torch.cuda.current_stream(self.streams[0].device)
+        for s in self.streams:
+            cur.wait_stream(s)
+
+    def pairs_fit(self, cam: dict, cfg: dict) -> bool:
+        """join(), then True if every slot that sorted this view fitted its
+        pairs; a slot that overflowed grows its buffers for its next frame."""
+        self.join()
+        key = (cam["width"], cam["height"], cfg["tile_size"])
+        ok = True
+        for r in self.slots:
+            b = r._bufs.get(key)
+            if b is not None and "n_pairs_dev" in b:
+                ok = r.pairs_fit(cam, cfg, b) and ok
+        return ok
+
+    def drop_view(self, cam: dict, cfg: dict) -> None:
+        """Free every slot's buffers for this view size (after join())."""
+        for r in self.slots:
+            r._bufs.pop((cam["width"], cam["height"], cfg["tile_size"]), None)

@@ -7,7 +7,8 @@ oracle run from the same FP32 scene.
   at full size, in the launch configuration the benchmark times, checked on
   sampled pixels that the oracle composites one by one.
 Plus invariants of the GPU path: plain mode equals the colour of gradient
-mode bit for bit, runs are deterministic, tile sizes agree.
+mode bit for bit, runs are deterministic, tile sizes agree, frames in flight
+on several streams equal frames rendered one at a time.
 """
 import numpy as np
 import pytest
@@ -176,6 +177,46 @@ def test_tile_sizes_agree(torch_mod):
         # identical fragment sequences; only the FP32 rounding of tile-relative
         # means differs (which can settle a rare near tie the other way)
         assert np.quantile(d, 0.999) < 1e-5 and (d > 1e-4).mean() < 1e-3
+
+
+@pytest.mark.parametrize("depth", [2, 3])
+def test_frames_in_flight_match_serial_frames(torch_mod, depth):
+    """FramePipeline: frames of different cameras in flight on several
+    streams at once give, bit for bit, the frames a lone renderer gives."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.render import FramePipeline, Renderer
+    sc = scenes.make_scene("clusters", 200000, 37, 3)
+    cfg = scenes.render_config(3, tile_size=16)
+    w, h, W, H = 480, 272, 960, 544
+    cams = [scenes.orbit_camera(w, h, az, el) for az, el in ((0, 0), (35, 10), (110, -15), (200, 5), (290, 20))]
+    serial = Renderer(sc)
+    refs, kmax = [], 0
+    for c in cams:
+        up, low = serial.render_upscaled(c, cfg, W, H)
+        refs.append((low.cpu().numpy(), up.cpu().numpy()))
+        kmax = max(kmax, serial._bufs[(w, h, 16)]["n_pairs"])
+    pipe = FramePipeline(Renderer(sc), depth)
+    for r in pipe.slots:  # room for every camera's pairs in every slot
+        b = r.project(cams[0], cfg)
+        r._ensure_capacity(b, cams[0], cfg, 2 * kmax + 1024)
+    nf = 2 * len(cams)
+    lows = [torch.empty((h, w, 12), dtype=torch.float32, device="cuda") for _ in range(nf)]
+    ups = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(nf)]
+    for f in range(nf):
+        def frame(r, c=cams[f % len(cams)], lo=lows[f], up=ups[f]):
+            b = r.project(c, cfg)
+            r.bin_sort_async(c, cfg, b)
+            r.raster(c, cfg, True, lo, b=b)
+            r.upscale(lo, W, H, up)
+        print(f"in flight: depth {depth} frame {f} slot {pipe.next_slot}", flush=True)
+        pipe.submit(frame)
+    assert pipe.pairs_fit(cams[0], cfg)
+    torch.cuda.synchronize()
+    for f in range(nf):
+        lo_ref, up_ref = refs[f % len(cams)]
+        np.testing.assert_array_equal(lows[f].cpu().numpy(), lo_ref)
+        np.testing.assert_array_equal(ups[f].cpu().numpy(), up_ref)
 
 
 def test_empty_and_degenerate_scenes(torch_mod, oracle):
