@@ -309,14 +309,15 @@ def run_gpu(args):
 
 def run_batch(args):
     """The batched stereo workload: autotuned setting, one captured graph per
-    frame for all 16 views; the direct baseline renders the 16 views at their
-    high-res sizes, also batched, graph-captured and tuned."""
+    frame for all 16 views, --inflight frames in flight; the direct baseline
+    renders the 16 views at their high-res sizes, also batched,
+    graph-captured, tuned and with the same number of frames in flight."""
     import torch
 
     from paper_2503_14171_amd import _lib as L
     from paper_2503_14171_amd import autotune, scenes
     from paper_2503_14171_amd.batch import ViewBatch
-    from paper_2503_14171_amd.render import Renderer
+    from paper_2503_14171_amd.render import FramePipeline, Renderer
 
     torch.cuda.set_device(0)
     sc = scenes.workload_scene("batch")
@@ -330,22 +331,28 @@ def run_batch(args):
     cfg = dict(cfg0, tile_size=tuned["tile_size"], batch=tuned["batch"])
     cfg_d = dict(cfg0, tile_size=tuned_d["tile_size"], batch=tuned_d["batch"])
 
-    def timed(vb, steps, warmup):
-        vb.capture()
-        vb.render()
-        for _ in range(warmup):
-            vb.launch()
+    def timed(make, steps, warmup):
+        """`steps` frames with args.inflight batches in flight (each its own
+        buffers, graph and stream); returns (ms per frame, the batches)."""
+        vbs = [make() for _ in range(args.inflight)]
+        for vb in vbs:
+            vb.capture()
+            vb.render()
+        pipe = FramePipeline(vbs)
+        for _ in range(max(warmup, 1) * len(vbs)):
+            pipe.submit(lambda vb: vb.launch())
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
-            vb.launch()
+            pipe.submit(lambda vb: vb.launch())
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t) / steps
-        assert vb.pairs_fit()
-        return ms
+        assert pipe.pairs_fit()
+        return ms, vbs
 
-    vb = ViewBatch(rd, cams, hi, cfg, band_rows=tuned["band_rows"])
-    ms = timed(vb, args.steps, args.warmup)
+    ms, vbs = timed(lambda: ViewBatch(rd, cams, hi, cfg, band_rows=tuned["band_rows"]), args.steps, args.warmup)
+    vb = vbs[0]
+    del vbs
     # per-stage times of the same chain, eager, with events between the calls
     r = rd
     ev = _events(torch, 5)
@@ -372,8 +379,9 @@ def run_batch(args):
     pairs = int(vb.n_pairs.item())
     up_imgs = [u.clone() for u in vb.views()[1]]
     del vb, nbl
-    vd = ViewBatch(rd, cams, hi, cfg_d, direct=True)
-    ms_d = timed(vd, max(3, args.steps // 2), 1)
+    ms_d, vds = timed(lambda: ViewBatch(rd, cams, hi, cfg_d, direct=True), max(3, args.steps // 2), 1)
+    vd = vds[0]
+    del vds
     psnrs = [_psnr(u.clamp(0, 1), d.clamp(0, 1)) for u, d in zip(up_imgs, vd.views()[1])]
     pairs_d = int(vd.n_pairs.item())
     del vd
@@ -506,8 +514,9 @@ def batch_line(args, res):
         "data": "synthetic",
         "config": {"workload": f"batch: {res['n']} Gaussians, SH degree 3, 8 stereo pairs (16 views): "
                                "4 pairs 720x800 -> 1440x1600 (x2), 4 pairs 480x540 -> 1440x1620 (x3); "
-                               "one HIP graph per frame",
+                               f"one HIP graph per frame, {args.inflight} frames in flight",
                    "gaussians": res["n"], "views": len(res["cams"]), "output_pixels": res["out_px"],
+                   "frames_in_flight": args.inflight,
                    "tuned": {k: tuned[k] for k in ("tile_size", "batch", "band_rows")},
                    "tuned_direct": {k: res["tuned_direct"][k] for k in ("tile_size", "batch")}},
         "roofline": {"kernel": "gs_raster_grad_views", "bound": "alu",

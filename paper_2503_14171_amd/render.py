@@ -153,10 +153,15 @@ class FramePipeline:
     sort passes with their scans, the pair emission, the raster, the
     upscale), and several of them launch far fewer workgroups than the chip
     holds or wait on a single-block scan, so a lone frame leaves compute units
-    idle under and between them.  Slot i renders on stream i with a renderer
-    of its own (pair lists, workspace and counters; the scene tensors are
-    shared), so the next frame's projection and sort fill what this frame's
+    idle under and between them.  Slot i renders on stream i with buffers of
+    its own, so the next frame's projection and sort fill what this frame's
     raster and scans leave.
+
+    ``slots`` is a :class:`Renderer`, to which the pipeline adds ``depth - 1``
+    siblings (own pair lists, workspace and counters; the scene tensors are
+    shared), or a list of objects that each hold one frame's buffers, such
+    as :class:`~paper_2503_14171_amd.batch.ViewBatch` instances over the same
+    scene and cameras.
 
     :meth:`submit` makes the slot's stream wait for the caller's current
     stream first, so inputs written there are seen; :meth:`join` makes the
@@ -165,12 +170,15 @@ class FramePipeline:
     reused on another stream only after :meth:`join`.
     """
 
-    def __init__(self, renderer: Renderer, depth: int = 2):
-        if depth < 1:
+    def __init__(self, slots, depth: int = 2):
+        if isinstance(slots, Renderer):
+            if depth < 1:
+                raise ValueError("a pipeline needs at least one slot")
+            slots = [slots] + [slots.sibling() for _ in range(depth - 1)]
+        self.slots = list(slots)
+        if not self.slots:
             raise ValueError("a pipeline needs at least one slot")
-        self.slots = [renderer] + [renderer.sibling() for _ in range(depth - 1)]
-        dev = torch.device(renderer.device)
-        self.streams = [torch.cuda.Stream(device=dev) for _ in range(depth)]  # default priority
+        self.streams = [torch.cuda.Stream() for _ in self.slots]  # default priority
         self._next = 0
 
     @property
@@ -183,34 +191,40 @@ class FramePipeline:
         return self._next
 
     def submit(self, frame) -> int:
-        """Call ``frame(renderer)`` with the next slot's stream current (its
+        """Call ``frame(slot)`` with the next slot's stream current (its
         launches go there); returns the slot index."""
         i = self._next
         self._next = (i + 1) % len(self.slots)
         s = self.streams[i]
-        s.wait_stream(torch.cuda.current_stream(s.device))
+        s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             frame(self.slots[i])
         return i
 
     def join(self) -> None:
-        cur = torch.cuda.current_stream(self.streams[0].device)
+        cur = torch.cuda.current_stream()
         for s in self.streams:
             cur.wait_stream(s)
 
-    def pairs_fit(self, cam: dict, cfg: dict) -> bool:
-        """join(), then True if every slot that sorted this view fitted its
-        pairs; a slot that overflowed grows its buffers for its next frame."""
+    def pairs_fit(self, *view) -> bool:
+        """join(), then True if every slot's last frame fitted its pairs; a
+        slot that overflowed grows its buffers for its next frame.  Renderer
+        slots take the view (``cam, cfg``) and check only the slots that
+        sorted it; other slots are asked ``slot.pairs_fit(*view)``."""
         self.join()
-        key = (cam["width"], cam["height"], cfg["tile_size"])
         ok = True
         for r in self.slots:
-            b = r._bufs.get(key)
-            if b is not None and "n_pairs_dev" in b:
-                ok = r.pairs_fit(cam, cfg, b) and ok
+            if isinstance(r, Renderer):
+                cam, cfg = view
+                b = r._bufs.get((cam["width"], cam["height"], cfg["tile_size"]))
+                if b is not None and "n_pairs_dev" in b:
+                    ok = r.pairs_fit(cam, cfg, b) and ok
+            else:
+                ok = r.pairs_fit(*view) and ok
         return ok
 
     def drop_view(self, cam: dict, cfg: dict) -> None:
-        """Free every slot's buffers for this view size (after join())."""
+        """Free every Renderer slot's buffers for this view size (after join())."""
         for r in self.slots:
-            r._bufs.pop((cam["width"], cam["height"], cfg["tile_size"]), None)
+            if isinstance(r, Renderer):
+                r._bufs.pop((cam["width"], cam["height"], cfg["tile_size"]), None)

@@ -151,6 +151,39 @@ def test_graph_replays_match_eager(torch_mod):
         np.testing.assert_array_equal(vb.up.cpu().numpy(), up_ref)
 
 
+def test_graphs_in_flight_match_eager(torch_mod):
+    """Two captured batches of different cameras replayed in flight on two
+    streams (FramePipeline) give what each gives alone, on every round."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.batch import ViewBatch
+    from paper_2503_14171_amd.render import FramePipeline, Renderer
+    sc = scenes.make_scene("scene", 60000, 47, 3)
+    rd = Renderer(sc)
+    cams, hi = _rig(8)
+    cfg = scenes.render_config(3)
+    vbs = [ViewBatch(rd, cams[:5], hi[:5], cfg), ViewBatch(rd, cams[5:], hi[5:], cfg)]
+    refs = []
+    for vb in vbs:
+        vb.render()
+        torch.cuda.synchronize()
+        refs.append((vb.low.cpu().numpy(), vb.up.cpu().numpy()))
+        vb.capture()
+    pipe = FramePipeline(vbs)
+    for rnd in range(3):
+        print(f"in flight: round {rnd}", flush=True)
+        for vb in vbs:
+            vb.low.fill_(float("nan"))
+            vb.up.fill_(float("nan"))
+        for _ in vbs:
+            pipe.submit(lambda vb: vb.launch())
+        assert pipe.pairs_fit()
+        torch.cuda.synchronize()
+        for vb, (low_ref, up_ref) in zip(vbs, refs):
+            np.testing.assert_array_equal(vb.low.cpu().numpy(), low_ref)
+            np.testing.assert_array_equal(vb.up.cpu().numpy(), up_ref)
+
+
 def test_pair_overflow_is_flagged_and_recovered(torch_mod):
     torch = torch_mod
     from paper_2503_14171_amd import _lib as L
