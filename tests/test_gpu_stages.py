@@ -122,23 +122,24 @@ def _tiles_xy(cam, tile):
     return -(-cam["width"] // tile), -(-cam["height"] // tile)
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_bin_sort_stable_under_depth_ties(gs, oracle, seed):
+@pytest.mark.parametrize("seed,tile", [(0, 16), (1, 16), (0, 64), (1, 64)])
+def test_bin_sort_stable_under_depth_ties(gs, oracle, seed, tile):
     """Few distinct depths: equal keys must keep index order; many pairs so
-    the sort runs several blocks and a two-level scan."""
+    the sort runs several blocks and a two-level scan.  3072 tiles take the
+    two-digit pair sort, 192 the single-digit one."""
     from paper_2503_14171_amd import scenes
     rng = np.random.default_rng(seed)
     n = 200000
     cam = scenes.make_camera(1024, 768)
-    cfg = scenes.render_config(0, tile_size=16)
-    tx, ty = _tiles_xy(cam, 16)
+    cfg = scenes.render_config(0, tile_size=tile)
+    tx, ty = _tiles_xy(cam, tile)
     x0 = rng.integers(0, tx, n)
     y0 = rng.integers(0, ty, n)
     w = rng.integers(0, 4, n)
     h = rng.integers(1, 4, n)
     rect = np.stack([x0, y0, np.minimum(x0 + w, tx), np.minimum(y0 + h, ty)], 1).astype(np.int32)
     d32 = rng.choice(np.array([0.5, 1.0, 1.0000001, 3.25, 7.0], np.float32), n)
-    print(f"bin_sort ties seed={seed}", flush=True)
+    print(f"bin_sort ties seed={seed} tile={tile}", flush=True)
     ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
     ref_ids, ref_ranges = oracle.tile_lists(d32, rect, tx, ty)
     assert ids.shape[0] > 65536 * 2
@@ -180,17 +181,19 @@ def _depth_set(kind, rng, n):
     raise ValueError(kind)
 
 
+@pytest.mark.parametrize("tile", [16, 32])
 @pytest.mark.parametrize("kind", _DEPTH_KINDS)
-def test_bin_sort_depth_key_ranges(gs, oracle, kind):
+def test_bin_sort_depth_key_ranges(gs, oracle, kind, tile):
     """Depth sets that need one to four radix passes over their bit range,
     with and without culled (+inf) splats, whose rectangles are empty as the
-    projection leaves them: the lists must equal a lexicographic sort."""
+    projection leaves them: the lists must equal a lexicographic sort (768
+    tiles: two-digit pair sort; 192: single-digit)."""
     from paper_2503_14171_amd import scenes
     rng = np.random.default_rng(_DEPTH_KINDS.index(kind) + 40)
     n = 70000
     cam = scenes.make_camera(512, 384)
-    cfg = scenes.render_config(0, tile_size=16)
-    tx, ty = _tiles_xy(cam, 16)
+    cfg = scenes.render_config(0, tile_size=tile)
+    tx, ty = _tiles_xy(cam, tile)
     x0 = rng.integers(0, tx, n)
     y0 = rng.integers(0, ty, n)
     w = rng.integers(1, 3, n)
@@ -198,7 +201,7 @@ def test_bin_sort_depth_key_ranges(gs, oracle, kind):
     rect = np.stack([x0, y0, np.minimum(x0 + w, tx), np.minimum(y0 + h, ty)], 1).astype(np.int32)
     d32 = _depth_set(kind, rng, n)
     rect[np.isinf(d32)] = 0
-    print(f"bin_sort depth keys kind={kind}", flush=True)
+    print(f"bin_sort depth keys kind={kind} tile={tile}", flush=True)
     ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
     ref_ids, ref_ranges = oracle.tile_lists(d32, rect, tx, ty)
     np.testing.assert_array_equal(ranges, ref_ranges)
@@ -434,16 +437,19 @@ def test_fd_bicubic_chain(gs, oracle, tiny_lowres):
         np.testing.assert_allclose(out.cpu().numpy(), ref, atol=5e-6, rtol=0)
 
 
-def test_bin_sort_views_matches_per_view_lexsort(gs, oracle):
-    """Two views of different tile grids sorted together (one with tiles beyond
-    x = 1022 and over-wide rectangles, i.e. escaped packed rectangles), with
-    culled splats: view after view, each view's lists must equal a
-    lexicographic sort of that view's records."""
+@pytest.mark.parametrize("sizes", [((8200, 160), (300, 200)), ((600, 40), (120, 64))])
+def test_bin_sort_views_matches_per_view_lexsort(gs, oracle, sizes):
+    """Two views of different tile grids sorted together, with over-wide
+    rectangles (escaped packed rectangles) and culled splats: view after
+    view, each view's lists must equal a lexicographic sort of that view's
+    records.  The first pair (one grid with tiles beyond x = 1022) takes the
+    two-digit pair sort, the second (75x5 + 15x8 = 495 tiles) the
+    single-digit one."""
     import torch
     from paper_2503_14171_amd import scenes
     rng = np.random.default_rng(91)
     n = 12000
-    cams = [scenes.make_camera(8200, 160), scenes.make_camera(300, 200)]
+    cams = [scenes.make_camera(w, h) for w, h in sizes]
     cfg = scenes.render_config(0, tile_size=8)
     depth, rect, refs = [], [], []
     for cam in cams:
@@ -468,7 +474,7 @@ def test_bin_sort_views_matches_per_view_lexsort(gs, oracle):
     ids = torch.full((K,), -7, dtype=torch.int32, device="cuda")
     ranges = torch.full((tiles, 2), -7, dtype=torch.int32, device="cuda")
     kdev = torch.zeros(1, dtype=torch.int64, device="cuda")
-    print("bin_sort views with escaped rectangles", flush=True)
+    print(f"bin_sort views with escaped rectangles {sizes}", flush=True)
     gs.gs_bin_sort_views(n, cams, cfg, _dev(np.concatenate(depth)), _dev(np.concatenate(rect)), K, ids,
                          ranges, kdev, ws)
     torch.cuda.synchronize()

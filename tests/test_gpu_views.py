@@ -218,8 +218,11 @@ def test_pair_overflow_is_flagged_and_recovered(torch_mod):
     b = rd.project(cam, cfg)
     rd._ensure_capacity(b, cam, cfg, 10)
     b["ranges"].fill_(-3)
+    ids_small = b["ids"]
+    ids_small.fill_(-5)
     rd.bin_sort_async(cam, cfg, b)
-    assert not rd.pairs_fit(cam, cfg, b)
+    assert not rd.pairs_fit(cam, cfg, b)  # (and grows b's buffers for the next frame)
+    assert (b["ranges"].cpu().numpy() == 0).all() and (ids_small.cpu().numpy() == -5).all()
     b2 = rd.project(cam, cfg)
     rd.bin_sort_async(cam, cfg, b2)
     assert rd.pairs_fit(cam, cfg, b2)
