@@ -5,7 +5,7 @@ scene whose inputs already sit in HBM: gs_project -> gs_bin_sort ->
 gs_raster_grad (colour + dI/dx, dI/dy, d2I/dxdy) -> gs_upscale_hermite.
 The default workload is the 3M-Gaussian scene (SH degree 3) rendered at
 960x540 and upscaled x4 to 3840x2160.  Throughput is high-res output
-megapixels per second with two frames in flight (--inflight), each on a
+megapixels per second with three frames in flight (--inflight), each on a
 stream and a set of buffers of its own; the same frames one at a time give
 the per-frame latency, reported beside it.
 
@@ -16,7 +16,7 @@ image against it, per-stage HIP-event times on each frame's stream, the
 raster kernel's arithmetic roofline and the upscaler's HBM roofline, and the
 FP64 CPU oracle on a bounded sample of the same frame (rank 0, N = 1).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene_x4] [--inflight 2]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene_x4] [--inflight 3]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -584,7 +584,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scene_x4", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", type=int, default=32)
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=3,
                     help="frames in flight on streams of their own (upscaled and direct paths alike)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle compositing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
