@@ -109,9 +109,9 @@ def run_gpu(args):
     lows = [torch.empty((h, w, 12), dtype=torch.float32, device="cuda") for _ in range(nsets)]
     ups = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(nsets)]
 
-    def frames(d, steps, warmup, with_events):
-        """Times `steps` upscaled frames with `d` in flight; per-stage events
-        on each frame's own stream."""
+    def frames(d, steps, warmup, with_events, cam=cam):
+        """Times `steps` upscaled frames of `cam` with `d` in flight;
+        per-stage events on each frame's own stream."""
         pipe = FramePipeline(rd, d)
         used = [0] * d
         last = [0]
@@ -184,7 +184,7 @@ def run_gpu(args):
     # quoted against
     direct_outs = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(depth)]
 
-    def time_direct(tile, d):
+    def time_direct(tile, d, cam_hi=cam_hi, steps=args.steps):
         cfg_d = dict(cfg, tile_size=tile)
         pipe = FramePipeline(rd, d)
 
@@ -213,12 +213,12 @@ def run_gpu(args):
         for _ in range(d + max(1, args.warmup)):
             direct_step()
         torch.cuda.synchronize()
-        devs = [_events(torch, 4) for _ in range(args.steps)]
+        devs = [_events(torch, 4) for _ in range(steps)]
         t0 = time.perf_counter()
-        for k in range(args.steps):
+        for k in range(steps):
             direct_step(devs[k])
         torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        ms = 1e3 * (time.perf_counter() - t0) / steps
         assert pipe.pairs_fit(cam_hi, cfg_d)
         st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in devs]).mean(0)
         if tile != cfg["tile_size"]:
@@ -290,10 +290,28 @@ def run_gpu(args):
     up_gbs_launch = up_bytes / (up_launch_ms * 1e-3) / 1e9
     value = W * H / (ms_step * 1e-3) / 1e6
     direct_value = W * H / (ms_direct * 1e-3) / 1e6
+    # the same scene from 8 orbit cameras (radius 3, azimuth k x 45 deg,
+    # elevation 15 deg), as the paper averages over test cameras: upscaled
+    # frames and the direct render at list tiles 32 and 64 (the better one),
+    # same frames in flight; last, since it reuses the frame's buffers
+    orbit = None
+    if not args.no_orbit:
+        n_o = max(3, min(args.steps, 10))
+        per = []
+        for k in range(8):
+            cam_o = scenes.orbit_camera(w, h, 45.0 * k, 15.0)
+            cam_oh = scenes.scale_camera(cam_o, W, H)
+            ms_up = frames(depth, n_o, 2, False, cam_o)[0]
+            ms_d = min(time_direct(t, depth, cam_oh, n_o)[0] for t in (32, 64))
+            per.append((ms_up, ms_d))
+        ups_ms = np.array([p[0] for p in per])
+        dir_ms = np.array([p[1] for p in per])
+        orbit = dict(ms=ups_ms, direct_ms=dir_ms, steps=n_o)
+
     best = dict(tile=best_tile, ms_per_frame=direct_all[best_tile][0],
                 value=W * H / (direct_all[best_tile][0] * 1e-3) / 1e6,
                 by_tile={t: round(v[0], 4) for t, v in direct_all.items()})
-    return dict(best_direct=best, comparators=comparators,
+    return dict(best_direct=best, comparators=comparators, orbit=orbit,
         name=name, s=s, w=w, h=h, W=W, H=H, n=rd.n, cfg=cfg, value=value, ms_step=ms_step,
         stages_ms=dict(project=st_ms[0], bin_sort=st_ms[1], raster_grad=st_ms[2], upscale=st_ms[3]),
         inflight=depth, ms_serial=ms_serial, ms_direct_serial=ms_direct_serial,
@@ -540,6 +558,52 @@ def batch_line(args, res):
     }
 
 
+def orbit_line(res, W, H):
+    o = res["orbit"]
+    if o is None:
+        return None
+    sp = o["direct_ms"] / o["ms"]
+    return {"cameras": "orbit radius 3, azimuth 0, 45, ..., 315 deg, elevation 15 deg",
+            "steps_per_camera": o["steps"],
+            "ms_per_frame": [round(float(v), 4) for v in o["ms"]],
+            "direct_best_ms_per_frame": [round(float(v), 4) for v in o["direct_ms"]],
+            "median_value": round(float(W * H / (np.median(o["ms"]) * 1e-3) / 1e6), 2),
+            "median_speedup_vs_best_direct": round(float(np.median(sp)), 3),
+            "min_speedup_vs_best_direct": round(float(sp.min()), 3)}
+
+
+def cpu_tiny_child():
+    """Child process (OMP_NUM_THREADS=1, no GPU): the FP64 oracle on the whole
+    tiny frame (10k Gaussians, 128x128 with derivatives, upscaled x2 to
+    256x256); prints one JSON line."""
+    from oracle import oracle
+    from paper_2503_14171_amd import scenes
+    sc = scenes.workload_scene("tiny")
+    cam = scenes.workload_camera("tiny")
+    cfg = scenes.render_config(sc["sh_degree"])
+    W, H = 2 * cam["width"], 2 * cam["height"]
+    t0 = time.perf_counter()
+    img = oracle.render(sc, cam, cfg)["img"]
+    oracle.upscale(img, W, H)
+    t = time.perf_counter() - t0
+    print(json.dumps({"seconds": t, "threads": oracle.num_threads(), "W": W, "H": H}), flush=True)
+
+
+def cpu_single_thread_tiny():
+    """The tiny frame on one host thread, in a CPU-only child process (the
+    oracle's OpenMP runtime reads its thread count once per process)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-tiny-child"],
+                       capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-300:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": round(d["W"] * d["H"] / d["seconds"] / 1e6, 6), "unit": "Mpix/s",
+            "cores": d["threads"], "seconds_per_frame": round(d["seconds"], 2),
+            "workload": "tiny: 10k Gaussians, 128x128 with derivatives, upscaled x2 to 256x256, whole frame"}
+
+
 def cpu_baseline(res, budget_s):
     """The FP64 oracle on a bounded sample of the same frame: projection and
     depth order of every Gaussian, compositing of a random sample of low-res
@@ -588,6 +652,8 @@ def main():
                     help="frames in flight on streams of their own (upscaled and direct paths alike)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle compositing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-orbit", action="store_true", help="skip the 8 orbit-camera timings")
+    ap.add_argument("--cpu-tiny-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (a reference for HBM counters)")
     args = ap.parse_args()
@@ -595,6 +661,14 @@ def main():
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.cpu_tiny_child:
+        cpu_tiny_child()
+        return
+    # before anything touches the GPU: the single-thread oracle run is a child process
+    tiny_1t = None
+    if not args.no_cpu_baseline and WORKLOADS[args.workload][0] not in ("batch", "train"):
+        tiny_1t = cpu_single_thread_tiny()
 
     if WORKLOADS[args.workload][0] == "batch":
         res = run_batch(args)
@@ -659,6 +733,7 @@ def main():
                         "ms_by_tile": res["best_direct"]["by_tile"]},
         "speedup_vs_best_direct": round(res["value"] / res["best_direct"]["value"], 3),
         "psnr_vs_direct_db": round(res["psnr"], 2),
+        "orbit_cameras": orbit_line(res, W, H),
         "comparators": {"psnr_fd_bicubic_db": round(res["comparators"]["psnr_fd_bicubic"], 2),
                         "psnr_torch_bicubic_db": round(res["comparators"]["psnr_torch_bicubic"], 2),
                         "fd_slopes_ms": round(res["comparators"]["fd_slopes_ms"], 4),
@@ -668,6 +743,7 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(res, args.cpu_budget)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 6)
+        line["cpu_baseline"]["single_thread_tiny"] = tiny_1t
     print(json.dumps(line), flush=True)
 
 

@@ -48,3 +48,6 @@ def test_bench_line_fields(monkeypatch):
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], abs=1e-4)
     assert roof["traffic"] is None  # counters were taken on the scene workload only
     assert 0 < line["upscaler_roofline"]["frac"] < 1
+    orbit = line["orbit_cameras"]
+    assert len(orbit["ms_per_frame"]) == 8 and len(orbit["direct_best_ms_per_frame"]) == 8
+    assert orbit["median_value"] > 0 and orbit["median_speedup_vs_best_direct"] > 0
