@@ -177,6 +177,22 @@ def run_gpu(args):
     ue[1].record()
     torch.cuda.synchronize()
     up_launch_ms = ue[0].elapsed_time(ue[1]) / nup
+    # a plain device copy moving the upscaler's bytes (62.2 MB read + 62.2 MB
+    # written), back to back over 4 buffer pairs (> 256 MB MALL): the
+    # bandwidth a streaming kernel reaches on this GPU
+    cbytes = (w * h * UPSCALE_BYTES_LO + W * H * UPSCALE_BYTES_HI) // 2
+    csrc = [torch.empty(cbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0) for _ in range(4)]
+    cdst = [torch.empty_like(c) for c in csrc]
+    for k in range(4):
+        cdst[k].copy_(csrc[k])
+    ce = _events(torch, 2)
+    ce[0].record()
+    for k in range(16):
+        cdst[k % 4].copy_(csrc[k % 4])
+    ce[1].record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * cbytes / (ce[0].elapsed_time(ce[1]) / 16 * 1e-3) / 1e9
+    del csrc, cdst
 
     # direct full-resolution render (plain compositing) on the same GPU, with
     # the same number of frames in flight, at the frame's own tile size and at
@@ -321,7 +337,7 @@ def run_gpu(args):
                     stages_ms=dict(project=dstage[0], bin_sort=dstage[1], raster_plain=dstage[2]),
                     pairs=pairs_hi, blended_fragments=frags_hi),
         psnr=psnr, frags=frags, pairs=pairs, achieved_tflops=achieved, up_gbs=up_gbs,
-        up_gbs_launch=up_gbs_launch, up_launch_ms=up_launch_ms,
+        up_gbs_launch=up_gbs_launch, up_launch_ms=up_launch_ms, copy_gbs=copy_gbs,
         up_bytes=up_bytes, scene=sc, cam=cam)
 
 
@@ -714,6 +730,8 @@ def main():
                               "frac": round(res["up_gbs_launch"] / HBM_PEAK_GBS, 4),
                               "us_per_launch": round(1e3 * res["up_launch_ms"], 2),
                               "in_frame_achieved": round(res["up_gbs"], 1),
+                              "copy_gbs": round(res["copy_gbs"], 1),
+                              "frac_of_copy": round(res["up_gbs_launch"] / res["copy_gbs"], 4),
                               "bytes": res["up_bytes"],
                               "traffic": measured_traffic("gs_upscale_hermite") if args.workload == "scene_x4" else None},
         "stages_ms": {k: round(v, 4) for k, v in res["stages_ms"].items()},
