@@ -166,7 +166,10 @@ def run_gpu(args):
     ms_step, st_ms, last_set = frames(depth, args.steps, args.warmup, True)
     # one frame at a time: the latency of a frame, and the stages with the GPU
     # to themselves
-    ms_serial, st_serial = frames(1, args.steps, args.warmup, True)[:2] if depth > 1 else (ms_step, st_ms)
+    # (the output sets then hold that pass's frames: last_set is its last one)
+    ms_serial, st_serial = ms_step, st_ms
+    if depth > 1:
+        ms_serial, st_serial, last_set = frames(1, args.steps, args.warmup, True)
     # the upscaler's own launch duration: back-to-back launches over the
     # rotating buffer sets between two events on the launch stream
     ue = _events(torch, 2)
