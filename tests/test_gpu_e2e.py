@@ -219,6 +219,45 @@ def test_frames_in_flight_match_serial_frames(torch_mod, depth):
         np.testing.assert_array_equal(ups[f].cpu().numpy(), up_ref)
 
 
+def test_frames_in_flight_recover_from_pair_overflow(torch_mod):
+    """Every slot starts with room for 64 pairs: the frames in flight
+    overflow, pairs_fit reports it and grows each slot, and the frames run
+    again equal the serial ones."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.render import FramePipeline, Renderer
+    sc = scenes.make_scene("clusters", 100000, 41, 3)
+    cfg = scenes.render_config(3, tile_size=32)
+    cam = scenes.orbit_camera(320, 192, 30.0, 10.0)
+    W, H = 640, 384
+    up_ref, low_ref = Renderer(sc).render_upscaled(cam, cfg, W, H)
+    up_ref, low_ref = up_ref.cpu().numpy(), low_ref.cpu().numpy()
+    pipe = FramePipeline(Renderer(sc), 2)
+    for r in pipe.slots:
+        b = r.project(cam, cfg)
+        r._ensure_capacity(b, cam, cfg, 64)
+    lows = [torch.full((192, 320, 12), float("nan"), device="cuda") for _ in range(2)]
+    ups = [torch.full((H, W, 3), float("nan"), device="cuda") for _ in range(2)]
+
+    def frame(r):
+        i = pipe.slots.index(r)
+        b = r.project(cam, cfg)
+        r.bin_sort_async(cam, cfg, b)
+        r.raster(cam, cfg, True, lows[i], b=b)
+        r.upscale(lows[i], W, H, ups[i])
+
+    for rnd in range(2):
+        print(f"overflow in flight: round {rnd}", flush=True)
+        for _ in range(2):
+            pipe.submit(frame)
+        fit = pipe.pairs_fit(cam, cfg)
+        assert fit == (rnd == 1)
+    torch.cuda.synchronize()
+    for i in range(2):
+        np.testing.assert_array_equal(lows[i].cpu().numpy(), low_ref)
+        np.testing.assert_array_equal(ups[i].cpu().numpy(), up_ref)
+
+
 def test_empty_and_degenerate_scenes(torch_mod, oracle):
     torch = torch_mod
     from paper_2503_14171_amd import scenes
