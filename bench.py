@@ -13,8 +13,10 @@ Beside it the script measures, on the same GPU and with the same number of
 frames in flight, the direct full-resolution render (gs_project +
 gs_bin_sort + plain gs_raster_grad at 3840x2160), the PSNR of the upscaled
 image against it, per-stage HIP-event times on each frame's stream, the
-raster kernel's arithmetic roofline and the upscaler's HBM roofline, and the
-FP64 CPU oracle on a bounded sample of the same frame (rank 0, N = 1).
+raster kernel's arithmetic roofline and the upscaler's HBM roofline (with a
+plain device copy of the same bytes as a reference), both paths from 8 orbit
+cameras, and the FP64 CPU oracle on a bounded sample of the same frame plus,
+on one thread, the whole tiny frame (rank 0, N = 1).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene_x4] [--inflight 3]
 Prints one JSON line.
