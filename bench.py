@@ -675,8 +675,6 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-orbit", action="store_true", help="skip the 8 orbit-camera timings")
     ap.add_argument("--cpu-tiny-child", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--copy-probe-mb", type=int, default=0,
-                    help="also run a plain device copy of this many MB (a reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1",
@@ -700,13 +698,6 @@ def main():
         print(json.dumps(train_line(args, res)), flush=True)
         return
     res = run_gpu(args)
-    if args.copy_probe_mb:
-        import torch
-        src = torch.empty(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
     name, s, w, h, W, H = (res[k] for k in ("name", "s", "w", "h", "W", "H"))
     line = {
         "metric": METRIC,
