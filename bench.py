@@ -665,8 +665,8 @@ def cpu_baseline(res, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="scene_x4", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", type=int, default=32)
     ap.add_argument("--inflight", type=int, default=3,
