@@ -20,6 +20,17 @@ def test_more_than_one_gpu_is_refused():
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
 
 
+def test_single_thread_oracle_child():
+    """The CPU baseline's single-thread run (a child process on one OpenMP
+    thread, no GPU) prints the whole tiny frame's time as one JSON line."""
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-tiny-child"],
+                       capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stderr[-500:]
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert d["threads"] == 1 and (d["W"], d["H"]) == (256, 256) and d["seconds"] > 0
+
+
 @pytest.mark.gpu
 def test_bench_line_fields(monkeypatch):
     torch = pytest.importorskip("torch")
