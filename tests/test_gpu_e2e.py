@@ -258,6 +258,46 @@ def test_frames_in_flight_recover_from_pair_overflow(torch_mod):
         np.testing.assert_array_equal(ups[i].cpu().numpy(), up_ref)
 
 
+def test_scene_x4_three_in_flight_equals_serial(torch_mod):
+    """The benchmark's launch configuration (3M-Gaussian scene, 960x540 with
+    derivatives, x4 to 3840x2160, 32x32 list tiles, three frames in flight)
+    gives, bit for bit, the serial frame that the sampled oracle test checks."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.render import FramePipeline, Renderer
+    sc = scenes.workload_scene("scene")
+    cam = scenes.workload_camera("scene")
+    cfg = scenes.render_config(sc["sh_degree"], tile_size=32)
+    W, H = 3840, 2160
+    rd = Renderer(sc)
+    print("scene x4: serial frame", flush=True)
+    up_ref, low_ref = rd.render_upscaled(cam, cfg, W, H)
+    up_ref, low_ref = up_ref.cpu().numpy(), low_ref.cpu().numpy()
+    pipe = FramePipeline(rd, 3)
+    lows = [torch.empty((540, 960, 12), dtype=torch.float32, device="cuda") for _ in range(3)]
+    ups = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(3)]
+
+    def frame(r):
+        i = pipe.slots.index(r)
+        b = r.project(cam, cfg)
+        r.bin_sort_async(cam, cfg, b)
+        r.raster(cam, cfg, True, lows[i], b=b)
+        r.upscale(lows[i], W, H, ups[i])
+
+    for rnd in range(3):
+        print(f"scene x4: three in flight, round {rnd}", flush=True)
+        for _ in range(3):
+            pipe.submit(frame)
+        if pipe.pairs_fit(cam, cfg):
+            break
+    else:
+        pytest.fail("pairs never fitted")
+    torch.cuda.synchronize()
+    for i in range(3):
+        np.testing.assert_array_equal(lows[i].cpu().numpy(), low_ref)
+        np.testing.assert_array_equal(ups[i].cpu().numpy(), up_ref)
+
+
 def test_empty_and_degenerate_scenes(torch_mod, oracle):
     torch = torch_mod
     from paper_2503_14171_amd import scenes
