@@ -38,8 +38,20 @@ import numpy as np
 METRIC = "upscaled output Mpix/s vs direct full-res raster (same GPU) at PSNR gap; BW %"
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP32_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA), no packed FP32
+VALU_TOPS = 39.32           # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz: VALU lane-operations per second
 # FP32 operations of the method per blended fragment (FMA = 2), grad and plain
 FLOP_PER_BLEND = {True: 64, False: 25}
+# VALU lane-op slots of the rasterizer's work (an exp counts 4 slots): per
+# evaluated fragment (offset, quadratic form, support test) and per blended
+# fragment on top of that (alpha, its derivatives, the blend), grad / plain
+SLOTS_EVAL = 16
+SLOTS_BLEND = {True: 35, False: 8}
+# Projection bytes per Gaussian: parameters read (means, log-scales,
+# quaternion, opacity: 44 B, plus 12 B per SH coefficient) and ~44 B written
+PROJ_BYTES_PARAMS, PROJ_BYTES_OUT = 44, 44
+# Bin/sort floor per (tile, splat) pair: the pair written once and read once
+# (8-byte key/value each way) plus the 4-byte id written and read
+BINSORT_BYTES_PER_PAIR = 24
 # Bytes the upscaler must move: 48 per low-res pixel read, 12 per output pixel written
 UPSCALE_BYTES_LO, UPSCALE_BYTES_HI = 48, 12
 
@@ -291,21 +303,28 @@ def run_gpu(args):
                        fd_slopes_ms=fev[0].elapsed_time(fev[1]) / 10,
                        fd_upscale_ms=fev[1].elapsed_time(fev[2]) / 10)
 
-    # algorithmic work of the raster launch: blended fragments (one extra,
-    # untimed launch with the per-pixel counter)
+    # algorithmic work of the raster launch: evaluated and blended fragments
+    # per pixel (one extra, untimed launch with the per-pixel counters)
+    nev = torch.empty((h, w), dtype=torch.int32, device="cuda")
     nbl = torch.empty((h, w), dtype=torch.int32, device="cuda")
-    rd.render(cam, cfg, True, lows[0], nbl)
-    frags = int(nbl.sum().item())
+    rd.render_counts(cam, cfg, True, lows[0], nev, nbl)
+    evals, frags = int(nev.sum().item()), int(nbl.sum().item())
+    nev_hi = torch.empty((H, W), dtype=torch.int32, device="cuda")
     nbl_hi = torch.empty((H, W), dtype=torch.int32, device="cuda")
     direct_ref = torch.empty_like(direct_out)
-    rd.render(cam_hi, cfg, False, direct_ref, nbl_hi)
-    frags_hi = int(nbl_hi.sum().item())
+    rd.render_counts(cam_hi, cfg, False, direct_ref, nev_hi, nbl_hi)
+    evals_hi, frags_hi = int(nev_hi.sum().item()), int(nbl_hi.sum().item())
+    del nev_hi, nbl_hi, direct_ref
     pairs = rd._bufs[(w, h, cfg["tile_size"])]["n_pairs"]
     pairs_hi = rd._bufs[(W, H, cfg["tile_size"])]["n_pairs"]
 
     ras_ms = st_ms[2]
-    achieved = frags * FLOP_PER_BLEND[True] / (ras_ms * 1e-3) / 1e12
-    achieved_serial = frags * FLOP_PER_BLEND[True] / (st_serial[2] * 1e-3) / 1e12
+    ops = SLOTS_EVAL * evals + SLOTS_BLEND[True] * frags
+    achieved = ops / (ras_ms * 1e-3) / 1e12
+    achieved_serial = ops / (st_serial[2] * 1e-3) / 1e12
+    flops_serial = frags * FLOP_PER_BLEND[True] / (st_serial[2] * 1e-3) / 1e12
+    proj_bytes = rd.n * (PROJ_BYTES_PARAMS + 12 * (cfg["sh_degree"] + 1) ** 2 + PROJ_BYTES_OUT)
+    sort_bytes = BINSORT_BYTES_PER_PAIR * pairs
     up_bytes = w * h * UPSCALE_BYTES_LO + W * H * UPSCALE_BYTES_HI
     up_gbs = up_bytes / (st_ms[3] * 1e-3) / 1e9
     up_gbs_launch = up_bytes / (up_launch_ms * 1e-3) / 1e9
@@ -340,8 +359,9 @@ def run_gpu(args):
                            upscale=st_serial[3]), achieved_serial=achieved_serial,
         direct=dict(value=direct_value, ms_per_frame=ms_direct,
                     stages_ms=dict(project=dstage[0], bin_sort=dstage[1], raster_plain=dstage[2]),
-                    pairs=pairs_hi, blended_fragments=frags_hi),
-        psnr=psnr, frags=frags, pairs=pairs, achieved_tflops=achieved, up_gbs=up_gbs,
+                    pairs=pairs_hi, blended_fragments=frags_hi, evaluated_fragments=evals_hi),
+        psnr=psnr, frags=frags, evals=evals, pairs=pairs, achieved_tops=achieved,
+        flops_serial=flops_serial, proj_bytes=proj_bytes, sort_bytes=sort_bytes, up_gbs=up_gbs,
         up_gbs_launch=up_gbs_launch, up_launch_ms=up_launch_ms, copy_gbs=copy_gbs,
         up_bytes=up_bytes, scene=sc, cam=cam)
 
@@ -413,11 +433,12 @@ def run_batch(args):
         acc += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
     st = acc / nrep
     nbl = torch.empty(sum(vb.lo_px), dtype=torch.int32, device="cuda")
-    L.gs_raster_grad_views(vb.splats, vb.ids, vb.ranges, vb.cams, vb.cfg, True, vb.low, nbl)
-    frags = int(nbl.sum().item())
+    nev = torch.empty_like(nbl)
+    L.gs_raster_fragment_counts(vb.splats, vb.ids, vb.ranges, vb.cams, vb.cfg, True, vb.low, nev, nbl)
+    frags, evals = int(nbl.sum().item()), int(nev.sum().item())
     pairs = int(vb.n_pairs.item())
     up_imgs = [u.clone() for u in vb.views()[1]]
-    del vb, nbl
+    del vb, nbl, nev
     ms_d, vds = timed(lambda: ViewBatch(rd, cams, hi, cfg_d, direct=True), max(3, args.steps // 2), 1)
     vd = vds[0]
     del vds
@@ -431,8 +452,9 @@ def run_batch(args):
                 tune_s=tune_s, ms_step=ms, value=out_px / (ms * 1e-3) / 1e6,
                 stages_ms=dict(project=st[0], bin_sort=st[1], raster_grad=st[2], upscale=st[3]),
                 direct=dict(value=out_px / (ms_d * 1e-3) / 1e6, ms_per_frame=ms_d, pairs=pairs_d),
-                psnr=float(np.mean(psnrs)), psnr_min=float(np.min(psnrs)), frags=frags, pairs=pairs,
-                achieved_tflops=frags * FLOP_PER_BLEND[True] / (st[2] * 1e-3) / 1e12,
+                psnr=float(np.mean(psnrs)), psnr_min=float(np.min(psnrs)), frags=frags, evals=evals,
+                pairs=pairs,
+                achieved_tops=(SLOTS_EVAL * evals + SLOTS_BLEND[True] * frags) / (st[2] * 1e-3) / 1e12,
                 up_gbs=up_bytes / (st[3] * 1e-3) / 1e9, up_bytes=up_bytes, out_px=out_px)
 
 
@@ -559,9 +581,11 @@ def batch_line(args, res):
                    "tuned": {k: tuned[k] for k in ("tile_size", "batch", "band_rows")},
                    "tuned_direct": {k: res["tuned_direct"][k] for k in ("tile_size", "batch")}},
         "roofline": {"kernel": "gs_raster_grad_views", "bound": "alu",
-                     "achieved": round(res["achieved_tflops"], 3), "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(res["achieved_tflops"] / FP32_VALU_TFLOPS, 4), "traffic": None,
-                     "units": f"{res['frags']} blended fragments x {FLOP_PER_BLEND[True]} FLOP"},
+                     "achieved": round(res["achieved_tops"], 3), "peak": VALU_TOPS,
+                     "unit": "TOP/s (VALU lane-ops)",
+                     "frac": round(res["achieved_tops"] / VALU_TOPS, 4), "traffic": None,
+                     "units": (f"{SLOTS_EVAL} x {res['evals']} evaluated + {SLOTS_BLEND[True]} x "
+                               f"{res['frags']} blended fragments")},
         "upscaler_roofline": {"kernel": "gs_upscale_hermite_views", "bound": "hbm",
                               "achieved": round(res["up_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(res["up_gbs"] / HBM_PEAK_GBS, 4), "bytes": res["up_bytes"],
@@ -720,15 +744,37 @@ def main():
         # stream over the timed frames), as the upscaler's figure below; with
         # frames in flight the launch shares the GPU with other frames' kernels
         "roofline": {"kernel": "gs_raster_grad", "bound": "alu",
-                     "achieved": round(res["achieved_serial"], 3), "peak": FP32_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(res["achieved_serial"] / FP32_VALU_TFLOPS, 4),
+                     "achieved": round(res["achieved_serial"], 3), "peak": VALU_TOPS,
+                     "unit": "TOP/s (VALU lane-ops)",
+                     "frac": round(res["achieved_serial"] / VALU_TOPS, 4),
                      "traffic": measured_traffic("gs_raster_grad") if (args.workload, args.tile) == ("scene_x4", 32) else None,
-                     "units": f"{res['frags']} blended fragments x {FLOP_PER_BLEND[True]} FLOP",
+                     "units": (f"{SLOTS_EVAL} x {res['evals']} evaluated + {SLOTS_BLEND[True]} x "
+                               f"{res['frags']} blended fragments"),
                      "ms_per_launch": round(res["stages_serial"]["raster_grad"], 4),
                      "measured": "one frame at a time (the launch alone on the GPU)",
-                     "in_flight_achieved": round(res["achieved_tflops"], 3),
-                     "in_flight_frac": round(res["achieved_tflops"] / FP32_VALU_TFLOPS, 4),
+                     "flop_achieved_tflops": round(res["flops_serial"], 3),
+                     "flop_frac": round(res["flops_serial"] / FP32_VALU_TFLOPS, 4),
+                     "flop_units": f"{res['frags']} blended fragments x {FLOP_PER_BLEND[True]} FLOP "
+                                   f"of {FP32_VALU_TFLOPS} TFLOP/s",
+                     "in_flight_achieved": round(res["achieved_tops"], 3),
+                     "in_flight_frac": round(res["achieved_tops"] / VALU_TOPS, 4),
                      "in_flight_ms_per_launch": round(res["stages_ms"]["raster_grad"], 4)},
+        "stage_rooflines": {
+            "project": {"bound": "hbm", "bytes": res["proj_bytes"],
+                        "units": f"{res['n']} Gaussians x (params + SH read, splat written)",
+                        "ms": round(res["stages_serial"]["project"], 4),
+                        "achieved": round(res["proj_bytes"] / (res["stages_serial"]["project"] * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(res["proj_bytes"] / (res["stages_serial"]["project"] * 1e-3) / 1e9
+                                      / HBM_PEAK_GBS, 4)},
+            "bin_sort": {"bound": "hbm", "bytes": res["sort_bytes"],
+                         "units": f"{res['pairs']} pairs x {BINSORT_BYTES_PER_PAIR} B",
+                         "ms": round(res["stages_serial"]["bin_sort"], 4),
+                         "achieved": round(res["sort_bytes"] / (res["stages_serial"]["bin_sort"] * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(res["sort_bytes"] / (res["stages_serial"]["bin_sort"] * 1e-3) / 1e9
+                                       / HBM_PEAK_GBS, 4)},
+            "measured": "one frame at a time, events on the frame's stream"},
         "upscaler_roofline": {"kernel": "gs_upscale_hermite", "bound": "hbm",
                               "achieved": round(res["up_gbs_launch"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(res["up_gbs_launch"] / HBM_PEAK_GBS, 4),
@@ -746,8 +792,8 @@ def main():
         "one_in_flight": {"ms_per_frame": round(res["ms_serial"], 4),
                           "value": round(W * H / (res["ms_serial"] * 1e-3) / 1e6, 2),
                           "stages_ms": {k: round(v, 4) for k, v in res["stages_serial"].items()},
-                          "raster_achieved": round(res["achieved_serial"], 3),
-                          "raster_frac": round(res["achieved_serial"] / FP32_VALU_TFLOPS, 4),
+                          "raster_achieved_tops": round(res["achieved_serial"], 3),
+                          "raster_frac": round(res["achieved_serial"] / VALU_TOPS, 4),
                           "direct_ms_per_frame": round(res["ms_direct_serial"], 4),
                           "speedup_vs_direct": round(res["ms_direct_serial"] / res["ms_serial"], 3)},
         "direct_best": {"tile": res["best_direct"]["tile"], "value": round(res["best_direct"]["value"], 2),
@@ -761,6 +807,9 @@ def main():
                         "fd_slopes_ms": round(res["comparators"]["fd_slopes_ms"], 4),
                         "fd_upscale_ms": round(res["comparators"]["fd_upscale_ms"], 4)},
         "pairs": {"lowres": res["pairs"], "direct": res["direct"]["pairs"]},
+        "fragments": {"lowres_evaluated": res["evals"], "lowres_blended": res["frags"],
+                      "direct_evaluated": res["direct"]["evaluated_fragments"],
+                      "direct_blended": res["direct"]["blended_fragments"]},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(res, args.cpu_budget)

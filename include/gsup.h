@@ -257,6 +257,22 @@ gs_status gs_raster_grad_views(const gs_splat* splats, const int32_t* sorted_ids
                                const gs_camera* cams, const gs_raster_cfg* cfg,
                                int32_t want_grads, float* out, int32_t* n_blend, void* stream);
 
+/* gs_raster_fragment_counts -- gs_raster_grad_views (same inputs and `out`)
+ * that also reports the rasterizer's work per pixel, for measuring it:
+ *   n_eval [sum H W] int32 (device)  list entries the pixel evaluated before
+ *                                    it stopped: splats of its tile list whose
+ *                                    support reaches its 8x8 pixel block, for
+ *                                    each of which d^T Q d is computed and
+ *                                    tested against the alpha_min support
+ *   n_blend [sum H W] int32 (device) fragments it blended (alpha >= alpha_min)
+ * Both are required.  The counters cost the launch a few instructions per
+ * fragment; gs_raster_grad_views is the call to time. */
+gs_status gs_raster_fragment_counts(const gs_splat* splats, const int32_t* sorted_ids,
+                                    const int32_t* tile_ranges, int32_t n_views,
+                                    const gs_camera* cams, const gs_raster_cfg* cfg,
+                                    int32_t want_grads, float* out, int32_t* n_eval,
+                                    int32_t* n_blend, void* stream);
+
 /* gs_upscale_hermite_views -- one launch for all views.  lo_sizes and
  * hi_sizes are HOST arrays [n_views][2] of (width, height); in holds the
  * views' [h_v, w_v, 12] buffers back to back, out their [H_v, W_v, 3] images.

@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
         L.gs_bin_sort_views.restype = ctypes.c_int
         L.gs_raster_grad_views.argtypes = [P, P, P, i32, cams_p, cfg_p, i32, P, P, P]
         L.gs_raster_grad_views.restype = ctypes.c_int
+        L.gs_raster_fragment_counts.argtypes = [P, P, P, i32, cams_p, cfg_p, i32, P, P, P, P]
+        L.gs_raster_fragment_counts.restype = ctypes.c_int
         L.gs_upscale_hermite_views.argtypes = [P, i32, ctypes.POINTER(i32), P, ctypes.POINTER(i32), i32, P]
         L.gs_upscale_hermite_views.restype = ctypes.c_int
         L.gs_raster_grad_views_train.argtypes = [P, P, P, i32, cams_p, cfg_p, P, P, P, P]
@@ -261,6 +263,16 @@ def gs_raster_grad_views(splats, sorted_ids, tile_ranges, cams, cfg: dict, want_
                                       _ptr(tile_ranges, torch.int32), len(cams), cameras(cams),
                                       ctypes.byref(raster_cfg(cfg)), 1 if want_grads else 0,
                                       _ptr(out, torch.float32), _ptr(n_blend, torch.int32), _stream(stream)))
+
+
+def gs_raster_fragment_counts(splats, sorted_ids, tile_ranges, cams, cfg: dict, want_grads: bool, out,
+                              n_eval, n_blend, stream=None) -> None:
+    """gs_raster_grad_views plus per-pixel evaluated and blended fragment counts (int32)."""
+    _check(lib().gs_raster_fragment_counts(_ptr(splats, torch.float32), _ptr(sorted_ids, torch.int32),
+                                           _ptr(tile_ranges, torch.int32), len(cams), cameras(cams),
+                                           ctypes.byref(raster_cfg(cfg)), 1 if want_grads else 0,
+                                           _ptr(out, torch.float32), _ptr(n_eval, torch.int32),
+                                           _ptr(n_blend, torch.int32), _stream(stream)))
 
 
 def gs_upscale_hermite_views(inp, lo_sizes, out, hi_sizes, band_rows: int = 0, stream=None) -> None:

@@ -189,19 +189,21 @@ gs_status bin_sort_impl(const char* fn, int64_t n, int32_t nv, const gs_camera* 
 gs_status raster_impl(const char* fn, const gs_splat* splats, const int32_t* sorted_ids,
                       const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,
                       const gs_raster_cfg* cfg, int32_t want_grads, float* out, int32_t* n_blend,
-                      void* stream) {
+                      int32_t* n_eval, void* stream) {
   GS_CHECK(check_views(fn, nv, cams));
   GS_CHECK(check_cfg(fn, cfg));
   if (!splats || !sorted_ids || !tile_ranges || !out)
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
   if (!aligned(splats, 16) || !aligned(tile_ranges, 8) || !aligned(out, want_grads ? 16 : 4) ||
-      !aligned(sorted_ids, 4) || (n_blend && !aligned(n_blend, 4)))
+      !aligned(sorted_ids, 4) || (n_blend && !aligned(n_blend, 4)) ||
+      (n_eval && !aligned(n_eval, 4)))
     return fail(GS_ERR_INVALID_ARGUMENT,
                 "%s: splats (and out with gradients) must be 16-byte aligned", fn);
   if (total_tiles(nv, cams, cfg->tile_size) >= (int64_t(1) << 31))
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: too many tiles", fn);
   return check_hip(launch_raster(splats, sorted_ids, tile_ranges, nv, cams, *cfg, want_grads != 0,
-                                 out, n_blend, nullptr, nullptr, static_cast<hipStream_t>(stream)),
+                                 out, n_blend, n_eval, nullptr, nullptr,
+                                 static_cast<hipStream_t>(stream)),
                    "raster launch");
 }
 
@@ -291,7 +293,7 @@ gs_status gs_raster_grad(const gs_splat* splats, const int32_t* sorted_ids,
                          int32_t* n_blend, void* stream) {
   g_msg[0] = 0;
   return raster_impl("gs_raster_grad", splats, sorted_ids, tile_ranges, 1, cam, cfg, want_grads,
-                     out, n_blend, stream);
+                     out, n_blend, nullptr, stream);
 }
 
 gs_status gs_upscale_hermite(const float* in, int32_t w, int32_t h, float* out, int32_t W,
@@ -340,7 +342,19 @@ gs_status gs_raster_grad_views(const gs_splat* splats, const int32_t* sorted_ids
                                int32_t want_grads, float* out, int32_t* n_blend, void* stream) {
   g_msg[0] = 0;
   return raster_impl("gs_raster_grad_views", splats, sorted_ids, tile_ranges, n_views, cams, cfg,
-                     want_grads, out, n_blend, stream);
+                     want_grads, out, n_blend, nullptr, stream);
+}
+
+gs_status gs_raster_fragment_counts(const gs_splat* splats, const int32_t* sorted_ids,
+                                    const int32_t* tile_ranges, int32_t n_views,
+                                    const gs_camera* cams, const gs_raster_cfg* cfg,
+                                    int32_t want_grads, float* out, int32_t* n_eval,
+                                    int32_t* n_blend, void* stream) {
+  g_msg[0] = 0;
+  if (!n_eval || !n_blend)
+    return fail(GS_ERR_INVALID_ARGUMENT, "gs_raster_fragment_counts: NULL count buffer");
+  return raster_impl("gs_raster_fragment_counts", splats, sorted_ids, tile_ranges, n_views, cams,
+                     cfg, want_grads, out, n_blend, n_eval, stream);
 }
 
 gs_status gs_upscale_hermite_views(const float* in, int32_t n_views, const int32_t* lo_sizes,
@@ -384,7 +398,7 @@ gs_status gs_raster_grad_views_train(const gs_splat* splats, const int32_t* sort
       !aligned(state, 16) || !aligned(last, 4) || !aligned(sorted_ids, 4))
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: splats, out and state must be 16-byte aligned", fn);
   return check_hip(launch_raster(splats, sorted_ids, tile_ranges, n_views, cams, *cfg, true, out,
-                                 nullptr, state, last, static_cast<hipStream_t>(stream)),
+                                 nullptr, nullptr, state, last, static_cast<hipStream_t>(stream)),
                    "raster launch");
 }
 

@@ -84,13 +84,14 @@ gs_status run_bin_sort(const BinSortPlan& plan, const ViewTiles& vt, const float
 
 // ---- rasterization (raster.hip) -----------------------------------------------
 // One launch over the tiles of all views; view v's pixels go to
-// out + (sum of earlier views' pixels) * channels, likewise n_blend.
+// out + (sum of earlier views' pixels) * channels, likewise n_blend / n_eval
+// (optional: fragments blended / evaluated per pixel).
 // state / last (optional): final T, T_x, T_y, T_xy per pixel and the end of
 // its walked list, for the backward pass.
 hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
                          const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,
                          const gs_raster_cfg& cfg, bool grads, float* out, int32_t* n_blend,
-                         float* state, int32_t* last, hipStream_t stream);
+                         int32_t* n_eval, float* state, int32_t* last, hipStream_t stream);
 // dsplat [n_records, 9] (zeroed here): mean x, mean y, conic a, b, c, opacity, rgb.
 hipError_t launch_raster_backward(const gs_splat* splats, const int32_t* sorted_ids,
                                   const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,

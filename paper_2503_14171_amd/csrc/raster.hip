@@ -46,9 +46,10 @@ using namespace raster_detail;
 namespace {
 
 
-// AUX: the per-pixel blend count and walk end are kept (n_blend or state
-// requested); the headline frame needs neither and saves two updates per
-// blended fragment.
+// AUX: the per-pixel fragment counts and walk end are kept (n_blend, n_eval
+// or state requested); the headline frame needs none of them and saves the
+// updates.  n_eval counts the list entries a pixel evaluates (its quadrant's
+// hits, alpha test computed) before it stops, n_blend those it blends.
 template <int TILE, bool GRAD, int BATCH, int SUB, bool AUX>
 __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
                                                             const gs_splat* __restrict__ splats,
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
                                                             const int2* __restrict__ ranges,
                                                             float* __restrict__ out,
                                                             int32_t* __restrict__ n_blend,
+                                                            int32_t* __restrict__ n_eval,
                                                             float4* __restrict__ state,
                                                             int32_t* __restrict__ last) {
   constexpr int NT = TILE * TILE;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
   float B0 = 0.f, B1 = 0.f, B2 = 0.f;
   float Bx0 = 0.f, Bx1 = 0.f, Bx2 = 0.f, By0 = 0.f, By1 = 0.f, By2 = 0.f;
   float Bxy0 = 0.f, Bxy1 = 0.f, Bxy2 = 0.f;
-  int nb = 0;
+  int nb = 0, ne = 0;
   int lastpos = rg.x;  // list position after the last blended fragment
 
   for (int base = rg.x; base < rg.y; base += BATCH) {
@@ -118,11 +120,9 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
         if (det > 0.f) {
           const float rx = sqrtf(fmaxf(c.w * q.z / det, 0.f)) + kCullMargin;
           const float ry = sqrtf(fmaxf(c.w * q.x / det, 0.f)) + kCullMargin;
-          // quadrant k holds pixel centres 8k .. 8k+7 (float -> int saturates)
-          const int qx0 = max(0, (int)ceilf((mx - rx - 7.f) * 0.125f));
-          const int qx1 = min(QX - 1, (int)floorf((mx + rx) * 0.125f));
-          const int qy0 = max(0, (int)ceilf((my - ry - 7.f) * 0.125f));
-          const int qy1 = min(QX - 1, (int)floorf((my + ry) * 0.125f));
+          int qx0, qx1, qy0, qy1;
+          quad_span<QX>(mx, rx, qx0, qx1);
+          quad_span<QX>(my, ry, qy0, qy1);
           const bool exact = q.x > 0.f && q.z > 0.f;
           const float ia = exact ? 1.f / q.x : 0.f, ic = exact ? 1.f / q.z : 0.f;
           for (int qy = qy0; qy <= qy1; ++qy)
@@ -162,6 +162,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
           const float u = fmaf(ga.z, dx, ga.w * dy);  // (Q d)_x
           const float v = fmaf(ga.w, dx, gb.x * dy);  // (Q d)_y
           const float q = fmaf(dx, u, dy * v);        // d^T Q d
+          if (AUX && !done) ++ne;
           if (!done && q <= gb.z) {                   // alpha >= alpha_min
             const float2 gc = s_c[j];
             // the exponent is >= log2(alpha_min) > -126: no denormal handling needed
@@ -221,6 +222,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
     o[2] = fmaf(T, p.bg[2], B2);
   }
   if (AUX && n_blend) n_blend[pix] = nb;
+  if (AUX && n_eval) n_eval[pix] = ne;
   if (AUX && state) {  // for the backward pass: final T and derivatives, end of the walked list
     state[pix] = make_float4(T, Tx, Ty, Txy);
     last[pix] = lastpos;
@@ -230,6 +232,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
 struct RasterOut {
   float* out;
   int32_t* n_blend;
+  int32_t* n_eval;
   float4* state;
   int32_t* last;
 };
@@ -238,12 +241,12 @@ template <int TILE, bool GRAD, int BATCH, int SUB>
 void launch(const RasterParams& p, const gs_splat* splats, const int32_t* ids, const int2* ranges,
             const RasterOut& o, hipStream_t stream) {
   const unsigned grid = (unsigned)tile_grid(p.tiles, SUB * SUB);
-  if (o.n_blend || o.state)
+  if (o.n_blend || o.n_eval || o.state)
     raster_kernel<TILE, GRAD, BATCH, SUB, true><<<grid, TILE * TILE, 0, stream>>>(
-        p, splats, ids, ranges, o.out, o.n_blend, o.state, o.last);
+        p, splats, ids, ranges, o.out, o.n_blend, o.n_eval, o.state, o.last);
   else
     raster_kernel<TILE, GRAD, BATCH, SUB, false><<<grid, TILE * TILE, 0, stream>>>(
-        p, splats, ids, ranges, o.out, o.n_blend, o.state, o.last);
+        p, splats, ids, ranges, o.out, o.n_blend, o.n_eval, o.state, o.last);
 }
 
 // List tiles of edge TILE * SUB, workgroups of TILE x TILE pixels.  batch
@@ -263,9 +266,9 @@ void launch_batch(int batch, const RasterParams& p, const gs_splat* splats, cons
 hipError_t launch_raster(const gs_splat* splats, const int32_t* sorted_ids,
                          const int32_t* tile_ranges, int32_t nv, const gs_camera* cams,
                          const gs_raster_cfg& cfg, bool grads, float* out, int32_t* n_blend,
-                         float* state, int32_t* last, hipStream_t stream) {
+                         int32_t* n_eval, float* state, int32_t* last, hipStream_t stream) {
   const RasterParams p = make_params(nv, cams, cfg);
-  const RasterOut o{out, n_blend, reinterpret_cast<float4*>(state), last};
+  const RasterOut o{out, n_blend, n_eval, reinterpret_cast<float4*>(state), last};
   const int2* r2 = reinterpret_cast<const int2*>(tile_ranges);
   if (cfg.tile_size == 8) {
     if (grads) launch_batch<8, true, 1>(cfg.batch, p, splats, sorted_ids, r2, o, stream);

@@ -187,10 +187,9 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
         if (det > 0.f) {
           const float rx = sqrtf(fmaxf(c.w * q.z / det, 0.f)) + kCullMargin;
           const float ry = sqrtf(fmaxf(c.w * q.x / det, 0.f)) + kCullMargin;
-          const int qx0 = max(0, (int)ceilf((mx - rx - 7.f) * 0.125f));
-          const int qx1 = min(QX - 1, (int)floorf((mx + rx) * 0.125f));
-          const int qy0 = max(0, (int)ceilf((my - ry - 7.f) * 0.125f));
-          const int qy1 = min(QX - 1, (int)floorf((my + ry) * 0.125f));
+          int qx0, qx1, qy0, qy1;
+          quad_span<QX>(mx, rx, qx0, qx1);
+          quad_span<QX>(my, ry, qy0, qy1);
           const bool exact = q.x > 0.f && q.z > 0.f;
           const float ia = exact ? 1.f / q.x : 0.f, ic = exact ? 1.f / q.z : 0.f;
           for (int qy = qy0; qy <= qy1; ++qy)

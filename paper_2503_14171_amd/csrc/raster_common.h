@@ -45,6 +45,16 @@ __device__ __forceinline__ void tile_block(int64_t bid, int sub2, int64_t& tile,
 // (covers FP32 rounding of the box and of the per-pixel alpha test).
 constexpr float kCullMargin = 0.25f;
 
+// Quadrants [k0, k1] along one axis (quadrant k holds the pixel centres
+// 8k .. 8k+7 of the workgroup) that the box [m - r, m + r] meets; empty when
+// k0 > k1.  Clamped in float before the conversion, since converting a float
+// outside the int range is undefined.
+template <int QX>
+__device__ __forceinline__ void quad_span(float m, float r, int& k0, int& k1) {
+  k0 = (int)fminf(fmaxf(ceilf((m - r - 7.f) * 0.125f), 0.f), (float)QX);
+  k1 = (int)fminf(fmaxf(floorf((m + r) * 0.125f), -1.f), (float)(QX - 1));
+}
+
 // Whether the ellipse {d^T Q d <= S} around (mx, my) reaches the 8x8 pixel
 // centres [x0, x0 + 7] x [y0, y0 + 7] widened by kCullMargin: the minimum of
 // the quadratic over that rectangle (zero if it holds the centre, else on an

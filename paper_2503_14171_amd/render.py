@@ -134,6 +134,15 @@ class Renderer:
         self.bin_sort(cam, cfg, b)
         return self.raster(cam, cfg, want_grads, out, n_blend, b)
 
+    def render_counts(self, cam: dict, cfg: dict, want_grads: bool, out, n_eval, n_blend):
+        """render() through gs_raster_fragment_counts: also the evaluated and
+        blended fragments per pixel (int32 [H, W] each)."""
+        b = self.project(cam, cfg)
+        self.bin_sort(cam, cfg, b)
+        L.gs_raster_fragment_counts(b["splats"], b["ids"], b["ranges"], [cam], cfg, want_grads, out, n_eval,
+                                    n_blend)
+        return out
+
     @staticmethod
     def upscale(lowres: torch.Tensor, W: int, H: int, out=None):
         if out is None:

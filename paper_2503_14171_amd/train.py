@@ -39,6 +39,9 @@ class TrainViews:
         self.d_low = torch.empty((self.lo_px, 12), dtype=f, device=device)
         self.d_splats = torch.empty((V * n1, 9), dtype=f, device=device)
         self.n_pairs = torch.zeros(1, dtype=torch.int64, device=device)
+        # forwards run so far; the backward of a forward whose saved buffers
+        # (lists, final state) a later forward overwrote must not run
+        self.generation = 0
         self.capacity = 0
         self._shrink_to = 0
         self._alloc(4 * V * self.n + 1024)
@@ -71,12 +74,24 @@ class TrainViews:
             self._alloc(int(k * 1.25) + 1024)
         L.gs_raster_grad_views_train(self.splats, self.ids, self.ranges, self.cams, self.cfg, self.low,
                                      self.state, self.last)
+        self.generation += 1
         up = torch.empty((self.hi_px, 3), dtype=torch.float32, device=self.device)
         L.gs_upscale_hermite_views(self.low, self.lo, up, self.hi)
         return up
 
-    def backward(self, d_up, means, log_scales, quats, opacity, sh):
-        """dL/d(means, log_scales, quats, opacity, sh) for dL/d(upscaled) = d_up."""
+    def backward(self, d_up, means, log_scales, quats, opacity, sh, generation: int | None = None):
+        """dL/d(means, log_scales, quats, opacity, sh) for dL/d(upscaled) = d_up.
+
+        Walks the lists and final transmittance state of the latest forward;
+        ``generation`` (the value of ``self.generation`` right after the
+        forward being differentiated) must name that forward, otherwise a
+        RuntimeError is raised: inverting the blend from another forward's
+        final state would give wrong gradients silently."""
+        if generation is not None and generation != self.generation:
+            raise RuntimeError(
+                f"TrainViews: backward of forward #{generation}, but forward #{self.generation} has "
+                "since overwritten the saved lists and state; run backward before the next forward "
+                "on the same TrainViews (or use one TrainViews per pending forward)")
         d_up = d_up.contiguous().to(torch.float32)
         L.gs_upscale_hermite_backward_views(d_up, self.lo, self.d_low, self.hi)
         L.gs_raster_grad_backward_views(self.splats, self.ids, self.ranges, self.cams, self.cfg, self.state,
@@ -101,12 +116,13 @@ class UpscaledRender(torch.autograd.Function):
         args = tuple(t.contiguous() for t in (means, log_scales, quats, opacity, sh))
         up = views.forward(*args)
         ctx.views = views
+        ctx.generation = views.generation
         ctx.save_for_backward(*args)
         return up
 
     @staticmethod
     def backward(ctx, d_up):
-        grads = ctx.views.backward(d_up, *ctx.saved_tensors)
+        grads = ctx.views.backward(d_up, *ctx.saved_tensors, generation=ctx.generation)
         return (*grads, None)
 
 

@@ -54,9 +54,19 @@ def test_bench_line_fields(monkeypatch):
     roof = line["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in roof, k
-    assert roof["bound"] == "alu" and roof["peak"] == 78.6
+    assert roof["bound"] == "alu" and roof["peak"] == 39.32
     # both printed rounded: frac to 4 decimals, achieved to 3
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], abs=1e-4)
+    # the work behind it: 16 lane-op slots per evaluated and 35 more per
+    # blended fragment, over the launch time
+    fr = line["fragments"]
+    assert fr["lowres_evaluated"] >= fr["lowres_blended"] > 0
+    ops = 16 * fr["lowres_evaluated"] + 35 * fr["lowres_blended"]
+    # (ms_per_launch is printed to 4 decimals: a few percent on the tiny frame)
+    assert roof["achieved"] == pytest.approx(ops / (roof["ms_per_launch"] * 1e-3) / 1e12, rel=0.03)
+    for st in ("project", "bin_sort"):
+        sr = line["stage_rooflines"][st]
+        assert sr["bound"] == "hbm" and 0 < sr["frac"] < 1
     assert roof["traffic"] is None  # counters were taken on the scene workload only
     assert 0 < line["upscaler_roofline"]["frac"] < 1
     orbit = line["orbit_cameras"]

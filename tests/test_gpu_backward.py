@@ -5,8 +5,15 @@
   gs_project_backward_views          vs oracle.project_vjp (FP64 central differences)
   UpscaledRender (the whole chain)   vs oracle.loss_grad and vs FP64 finite differences
                                         of the oracle's forward, 64 Gaussians at 32x32
-Gradients are compared per parameter group: the error relative to the
-group's largest reference magnitude must stay below 1e-3.
+Gradients are compared element by element with a mixed bound,
+|got - ref| <= 1e-3 |ref| + 1e-5 max|ref of the group| (the absolute floor
+covers elements whose reference is a cancellation of many contributions that
+FP32 atomics sum in another order).
+Also: a 1M-Gaussian scene at 480x270 (the training workload's density, and a
+near-opaque variant whose lists are walked back through many fragments with
+alpha close to 0.99) against the oracle's adjoint on sampled pixels, and the
+guard against running backward after a later forward overwrote the saved
+state.
 """
 import numpy as np
 import pytest
@@ -16,6 +23,7 @@ from parity_util import rounded_proj, splat_records
 pytestmark = pytest.mark.gpu
 
 REL = 1e-3
+ABS_FLOOR = 1e-5  # of the group's largest reference magnitude
 
 
 @pytest.fixture(scope="module")
@@ -35,8 +43,13 @@ def _dev(a, dtype=None):
 
 
 def _rel_err(got, ref):
-    scale = max(np.abs(ref).max(), 1e-30)
-    return float(np.abs(got - ref).max() / scale)
+    """Largest per-element error in units of the mixed bound
+    REL |ref| + ABS_FLOOR max|ref| (scaled so that < REL passes)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    floor = ABS_FLOOR * max(np.abs(ref).max(), 1e-30)
+    bound = REL * np.abs(ref) + floor
+    return float((np.abs(got - ref) / bound).max() * REL)
 
 
 def test_upscale_backward_matches_oracle(torch_mod):
@@ -201,20 +214,23 @@ def test_training_chain_matches_oracle_and_finite_differences(torch_mod, oracle)
         return tot
     base = {k: np.asarray(sc[k], np.float64) for k in oracle.PARAMS}
     checked = 0
-    for k in ("means", "opacity", "sh"):
+    for k in oracle.PARAMS:  # means, log-scales, quaternions, opacity, SH
         got = params[k].grad.cpu().numpy()
-        idx = np.unravel_index(int(np.argmax(np.abs(ref[k]))), ref[k].shape)
-        hstep = 1e-6 * max(1.0, abs(base[k][idx]))
-        up_s = dict(sc, **base)
-        dn_s = dict(sc, **base)
-        up_s[k] = base[k].copy()
-        dn_s[k] = base[k].copy()
-        up_s[k][idx] += hstep
-        dn_s[k][idx] -= hstep
-        fd = (lin_loss(up_s) - lin_loss(dn_s)) / (2 * hstep)
-        assert abs(got[idx] - fd) <= REL * max(abs(fd), 1e-12), (k, idx, got[idx], fd)
-        checked += 1
-    assert checked == 3
+        # the three largest entries of the group
+        for flat in np.argsort(-np.abs(ref[k]).reshape(-1))[:3]:
+            idx = np.unravel_index(int(flat), ref[k].shape)
+            hstep = 1e-6 * max(1.0, abs(base[k][idx]))
+            up_s = dict(sc, **base)
+            dn_s = dict(sc, **base)
+            up_s[k] = base[k].copy()
+            dn_s[k] = base[k].copy()
+            up_s[k][idx] += hstep
+            dn_s[k][idx] -= hstep
+            fd = (lin_loss(up_s) - lin_loss(dn_s)) / (2 * hstep)
+            print(f"  FD {k}{tuple(int(i) for i in idx)}: gpu {got[idx]:.6e} fd {fd:.6e}", flush=True)
+            assert abs(got[idx] - fd) <= REL * max(abs(fd), 1e-12), (k, idx, got[idx], fd)
+            checked += 1
+    assert checked == 15
 
 
 def test_backward_of_unseen_scene_is_zero(torch_mod):
@@ -239,3 +255,86 @@ def test_backward_of_unseen_scene_is_zero(torch_mod):
     for k, p in params.items():
         g = p.grad.cpu().numpy()
         assert np.isfinite(g).all() and (g == 0).all(), k
+
+
+@pytest.mark.parametrize("opaque", [False, True])
+def test_raster_backward_dense_scene_sampled(torch_mod, oracle, opaque):
+    """Raster backward on the training workload's density: 1M Gaussians of the
+    scene process at 480x270 (and a near-opaque variant, opacity 0.9-0.99,
+    whose lists stop after a few fragments with alpha near alpha_max).  The
+    loss weights G are non-zero on 240 sampled pixels only, so the oracle's
+    adjoint over those pixels is the whole reference.  Checks that recovering
+    the state before each fragment from the saved final state (T = T'/(1 -
+    alpha) and its derivatives) holds over long, dense lists in FP32."""
+    torch = torch_mod
+    from paper_2503_14171_amd import _lib as L
+    from paper_2503_14171_amd import scenes
+    sc = scenes.workload_scene("batch")
+    if opaque:
+        rng = np.random.default_rng(71)
+        sc["opacity"] = rng.uniform(0.9, 0.995, sc["opacity"].shape).astype(np.float32)
+    cam = scenes.orbit_camera(480, 270, 30.0, 10.0)
+    cfg = scenes.render_config(3, tile_size=16)
+    print(f"dense raster backward opaque={opaque}: setup", flush=True)
+    pr, b, low, state, last = _raster_setup(torch, oracle, sc, cam, cfg)
+    w, h = cam["width"], cam["height"]
+    order = oracle.depth_order(pr)
+    rng = np.random.default_rng(72 + int(opaque))
+    npx = 240
+    pix = rng.choice(w * h, npx, replace=False)
+    xs, ys = (pix % w).astype(np.float64), (pix // w).astype(np.float64)
+    print("dense raster backward: oracle forward at the samples", flush=True)
+    fwd = oracle.composite(pr, order, cfg, xs, ys)
+    keep = fwd["n_amb"] == 0  # near-tie pixels have several correct walks
+    Gs = rng.standard_normal((npx, 12))
+    Gs[~keep] = 0.0
+    G = np.zeros((w * h, 12), np.float32)
+    G[pix] = Gs.astype(np.float32)
+    n = sc["means"].shape[0]
+    d_splats = torch.empty((n, 9), dtype=torch.float32, device="cuda")
+    L.gs_raster_grad_backward_views(b["splats"], b["ids"], b["ranges"], [cam], cfg, state, last,
+                                    _dev(G), n, d_splats)
+    torch.cuda.synchronize()
+    got = d_splats.cpu().numpy()
+    print("dense raster backward: oracle adjoint", flush=True)
+    ref = oracle.composite_adjoint(pr, order, cfg, xs, ys, Gs.astype(np.float32))
+    nb = fwd["n_blend"][keep]
+    print(f"  {int(keep.sum())} pixels, blended fragments per pixel: mean {nb.mean():.1f}, max {nb.max()}",
+          flush=True)
+    # the lists really are walked back through several fragments per pixel
+    assert nb.mean() > (1.5 if opaque else 5.0)
+    touched = np.abs(ref).sum(1) > 0
+    assert touched.sum() > 100
+    # records no sampled pixel blends get exactly zero
+    assert (got[~touched] == 0).all()
+    for f, name in enumerate(oracle.SPLAT_GRAD):
+        e = _rel_err(got[:, f], ref[:, f])
+        print(f"  {name}: err {e:.2e} (mixed bound, pass < {REL:.0e})", flush=True)
+        assert e < REL, name
+
+
+def test_backward_after_a_later_forward_raises(torch_mod):
+    """Two forwards on one TrainViews, then the first one's backward: the
+    saved lists and final state belong to the second forward, so backward
+    must refuse instead of returning wrong gradients.  The second forward's
+    backward still runs."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.train import TrainViews, UpscaledRender
+    sc = scenes.make_scene("clusters", 2000, 73, 1)
+    cams = [scenes.make_camera(40, 30)]
+    cfg = scenes.render_config(1)
+    tv = TrainViews(2000, cams, [(80, 60)], cfg)
+    params = {k: _dev(sc[k]).requires_grad_(True) for k in ("means", "log_scales", "quats", "opacity", "sh")}
+    args = [params[k] for k in ("means", "log_scales", "quats", "opacity", "sh")]
+    print("stale backward: two forwards", flush=True)
+    up1 = UpscaledRender.apply(*args, tv)
+    up2 = UpscaledRender.apply(*args, tv)
+    with pytest.raises(RuntimeError, match="overwritten"):
+        up1.sum().backward()
+    for p in args:
+        p.grad = None
+    (up2 * up2).sum().backward()
+    torch.cuda.synchronize()
+    assert all(np.isfinite(p.grad.cpu().numpy()).all() for p in args)
+    assert np.abs(params["means"].grad.cpu().numpy()).max() > 0

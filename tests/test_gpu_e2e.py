@@ -3,9 +3,13 @@ gs_raster_grad -> gs_upscale_hermite) on a synthetic scene against the FP64
 oracle run from the same FP32 scene.
 
 * tiny (10k Gaussians, 128x128 -> 256x256): every pixel of every buffer.
-* clusters (500k, 960x540 -> 1920x1080) and scene (3M, 960x540 -> x2/x3/x4)
-  at full size, in the launch configuration the benchmark times, checked on
-  sampled pixels that the oracle composites one by one.
+* clusters (500k, 960x540 -> 1920x1080) and scene (3M, 960x540 -> x4, and
+  the fractional / per-axis factors) at full size, at the benchmark's 32x32
+  list tiles (scene x4 also at 16x16), checked on sampled pixels that the
+  oracle composites one by one; for scene x4 the samples are stratified
+  (densest list tiles, list-tile and sub-tile borders, uniform).
+* the direct 3840x2160 render of the scene (the speed-up's denominator and
+  the PSNR reference) at 64x64 list tiles, on stratified samples.
 Plus invariants of the GPU path: plain mode equals the colour of gradient
 mode bit for bit, runs are deterministic, tile sizes agree, frames in flight
 on several streams equal frames rendered one at a time.
@@ -102,7 +106,52 @@ def test_e2e_tiny_all_pixels(torch_mod, oracle):
         assert_within(e_up.reshape(-1, 3), masked.reshape(-1))
 
 
-def _full_size_case(torch, oracle, name, scale, samples_low, samples_hi, tile=16):
+def _tile_density(oracle, proj, w, h, tile):
+    """Pairs per list tile from the oracle's own tile rectangles, [tiles_y, tiles_x]."""
+    rect = oracle.tile_rects(proj, w, h, tile)
+    tx, ty = -(-w // tile), -(-h // tile)
+    dens = np.zeros((ty + 1, tx + 1), np.int64)
+    ok = (rect[:, 2] > rect[:, 0]) & (rect[:, 3] > rect[:, 1])
+    r = rect[ok]
+    # 2D difference array: +1 on the rectangle's corners, then running sums
+    np.add.at(dens, (r[:, 1], r[:, 0]), 1)
+    np.add.at(dens, (r[:, 1], r[:, 2]), -1)
+    np.add.at(dens, (r[:, 3], r[:, 0]), -1)
+    np.add.at(dens, (r[:, 3], r[:, 2]), 1)
+    return dens.cumsum(0).cumsum(1)[:ty, :tx]
+
+
+def _stratified_pixels(rng, w, h, tile, dens, n_dense, n_border, n_uniform, n_top=4):
+    """Sample pixels (xs, ys): n_dense inside the n_top list tiles with the
+    most pairs, n_border on list-tile and 16x16 sub-tile borders (first or
+    last row / column of a sub-tile, where a workgroup's or a quadrant's
+    staging decisions change), and n_uniform uniformly over the image."""
+    tx = dens.shape[1]
+    top = np.argsort(-dens.reshape(-1))[:n_top]
+    k = rng.integers(0, n_top, n_dense)
+    t = top[k]
+    x0, y0 = (t % tx) * tile, (t // tx) * tile
+    xd = np.minimum(x0 + rng.integers(0, tile, n_dense), w - 1)
+    yd = np.minimum(y0 + rng.integers(0, tile, n_dense), h - 1)
+    # border pixels: a random sub-tile, then a random pixel on its edge
+    sub = 16 if tile >= 16 else tile
+    xb = rng.integers(0, w, n_border)
+    yb = rng.integers(0, h, n_border)
+    side = rng.integers(0, 4, n_border)
+    xb = np.where(side == 0, (xb // sub) * sub, np.where(side == 1, np.minimum((xb // sub) * sub + sub - 1, w - 1), xb))
+    yb = np.where(side == 2, (yb // sub) * sub, np.where(side == 3, np.minimum((yb // sub) * sub + sub - 1, h - 1), yb))
+    xu = rng.integers(0, w, n_uniform)
+    yu = rng.integers(0, h, n_uniform)
+    return np.concatenate([xd, xb, xu]), np.concatenate([yd, yb, yu])
+
+
+def _full_size_case(torch, oracle, name, scale, samples_low, samples_hi, tile=32, stratified=None):
+    """The full-size workload frame at list tile ``tile`` (the benchmark's is
+    32) against the oracle on sampled pixels.  ``stratified`` = (dense,
+    border) sample counts taken on top of the uniform ones: pixels of the four
+    list tiles with the most pairs and pixels on list-tile / sub-tile borders,
+    for the low-res image and (through the cells that serve them) the
+    upscaled one."""
     from paper_2503_14171_amd import scenes
     from paper_2503_14171_amd.render import Renderer
     sc = scenes.workload_scene(name)
@@ -122,19 +171,64 @@ def _full_size_case(torch, oracle, name, scale, samples_low, samples_hi, tile=16
     proj = oracle.project(sc, cam, cfg)
     order = oracle.depth_order(proj)
     rng = np.random.default_rng(7)
-    xs = rng.integers(0, w, samples_low)
-    ys = rng.integers(0, h, samples_low)
-    print(f"e2e {name}: oracle nodes", flush=True)
+    if stratified:
+        n_dense, n_border = stratified
+        dens = _tile_density(oracle, proj, w, h, tile)
+        xs, ys = _stratified_pixels(rng, w, h, tile, dens, n_dense, n_border, samples_low)
+    else:
+        xs = rng.integers(0, w, samples_low)
+        ys = rng.integers(0, h, samples_low)
+    print(f"e2e {name}: oracle nodes ({xs.size} low-res pixels)", flush=True)
     ref = _oracle_nodes(oracle, proj, order, cfg, xs, ys)
     err, masked = best_variant_error(low[ys, xs], ref)
-    report(f"e2e_{name}_lowres_sampled", summarize(err, masked, ref["out"]))
-    assert_within(err, masked, max_masked_frac=1e-2)
+    report(f"e2e_{name}_t{tile}_lowres_sampled", summarize(err, masked, ref["out"]))
+    assert_within(err, masked)
     print(f"e2e {name}: oracle upscaled samples", flush=True)
-    e_up, amb = _check_upscaled_samples(oracle, proj, order, cfg, (w, h), (W, H), up, samples_hi, 8)
+    if stratified:
+        # output pixels served by the cells of the sampled low-res pixels
+        # (dense tiles and borders), plus uniform ones
+        n_dense, n_border = stratified
+        cell_x, cell_y = xs[: n_dense + n_border], ys[: n_dense + n_border]
+        pick = rng.integers(0, cell_x.size, samples_hi)
+        X = np.minimum(np.floor((np.minimum(cell_x[pick], w - 2) + 0.5 + rng.random(samples_hi)) * W / w),
+                       W - 1).astype(np.int64)
+        Y = np.minimum(np.floor((np.minimum(cell_y[pick], h - 2) + 0.5 + rng.random(samples_hi)) * H / h),
+                       H - 1).astype(np.int64)
+        # and the four image corners (extrapolated border cells)
+        X = np.concatenate([X, rng.integers(0, W, samples_hi), [0, W - 1, 0, W - 1]])
+        Y = np.concatenate([Y, rng.integers(0, H, samples_hi), [0, 0, H - 1, H - 1]])
+        e_up, amb = _check_upscaled_pixels(oracle, proj, order, cfg, (w, h), (W, H), up, X, Y)
+    else:
+        e_up, amb = _check_upscaled_samples(oracle, proj, order, cfg, (w, h), (W, H), up, samples_hi, 8)
     tag = f"{sx}x{sy}" if sx != sy else f"{sx}"
-    report(f"e2e_{name}_x{tag}_upscaled_sampled", summarize(e_up, amb))
-    assert_within(e_up, amb, max_masked_frac=1e-2)
+    report(f"e2e_{name}_t{tile}_x{tag}_upscaled_sampled", summarize(e_up, amb))
+    assert_within(e_up, amb)
     return rd, cam, cfg, low, up
+
+
+def _check_upscaled_pixels(oracle, proj, order, cfg, low_wh, hi_wh, up_gpu, X, Y):
+    """As _check_upscaled_samples at the given high-res pixels (X, Y)."""
+    (w, h), (W, H) = low_wh, hi_wh
+    X = np.asarray(X, np.int64)
+    Y = np.asarray(Y, np.int64)
+    n = X.size
+    i, j = oracle.upscale_cell(X, Y, w, h, W, H)
+    xs = np.concatenate([i, i + 1, i, i + 1])
+    ys = np.concatenate([j, j, j + 1, j + 1])
+    nodes = _oracle_nodes(oracle, proj, order, cfg, xs, ys)
+    u = (X + 0.5) * w / W - 0.5 - i
+    vv = (Y + 0.5) * h / H - 0.5 - j
+    err = np.zeros((n, 3))
+    masked = np.zeros(n, bool)
+    for s in range(n):
+        corners = [node_variants(nodes, c * n + s) for c in range(4)]
+        cand = upscaled_candidates(oracle, corners, u[s], vv[s])
+        if cand is None:
+            masked[s] = True
+            continue
+        e = np.abs(cand - up_gpu[Y[s], X[s]][None])
+        err[s] = e[np.argmin(e.max(1))]
+    return err, masked
 
 
 def test_e2e_clusters_full_size_sampled(torch_mod, oracle):
@@ -142,8 +236,14 @@ def test_e2e_clusters_full_size_sampled(torch_mod, oracle):
 
 
 def test_e2e_scene_x4_full_size_sampled(torch_mod, oracle):
+    """The benchmark's frame: 3M Gaussians, 960x540 with derivatives at 32x32
+    list tiles, x4 to 3840x2160; 1000 low-res pixels (400 in the four list
+    tiles with the most pairs, 200 on list-tile / sub-tile borders, 400
+    uniform) and 504 output pixels (300 served by those cells, 200 uniform,
+    the 4 corners) against the oracle."""
     torch = torch_mod
-    rd, cam, cfg, low, up = _full_size_case(torch, oracle, "scene", 4, 250, 100)
+    rd, cam, cfg, low, up = _full_size_case(torch, oracle, "scene", 4, 400, 200, tile=32,
+                                            stratified=(400, 200))
     # the same frame again: bit-identical (no atomics in the compositing)
     up2, low2 = rd.render_upscaled(cam, cfg, up.shape[1], up.shape[0])
     torch.cuda.synchronize()
@@ -155,28 +255,81 @@ def test_e2e_scene_x4_full_size_sampled(torch_mod, oracle):
     assert np.array_equal(plain.cpu().numpy(), low[..., :3])
 
 
+def test_e2e_scene_x4_list_tile_16_sampled(torch_mod, oracle):
+    _full_size_case(torch_mod, oracle, "scene", 4, 250, 100, tile=16, stratified=(100, 100))
+
+
 @pytest.mark.parametrize("name,scale", [("clusters", 1.5), ("scene", 2.5), ("clusters", (4, 3)),
                                         ("clusters", (2.25, 1.75))])
 def test_e2e_fractional_and_per_axis_scales(torch_mod, oracle, name, scale):
     _full_size_case(torch_mod, oracle, name, scale, 120, 150)
 
 
-def test_tile_sizes_agree(torch_mod):
+def test_direct_4k_render_tile64_sampled(torch_mod, oracle):
+    """The speed-up's denominator and the PSNR reference: the direct 3840x2160
+    render of the 3M-Gaussian scene (plain compositing at the high-res
+    camera, 64x64 list tiles, the benchmark's best direct setting) against the
+    oracle's composite at the same camera on 900 sampled pixels (300 in the
+    four densest list tiles, 300 on 64x64 / 16x16 tile borders, 300
+    uniform)."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.render import Renderer
+    sc = scenes.workload_scene("scene")
+    cam_hi = scenes.scale_camera(scenes.workload_camera("scene"), 3840, 2160)
+    cfg = scenes.render_config(sc["sh_degree"], tile_size=64)
+    print("direct 4K tile 64: GPU", flush=True)
+    out = Renderer(sc).render(cam_hi, cfg, want_grads=False)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    assert out.shape == (2160, 3840, 3) and np.isfinite(out).all()
+    print("direct 4K: oracle projection", flush=True)
+    proj = oracle.project(sc, cam_hi, cfg)
+    order = oracle.depth_order(proj)
+    dens = _tile_density(oracle, proj, 3840, 2160, 64)
+    rng = np.random.default_rng(11)
+    xs, ys = _stratified_pixels(rng, 3840, 2160, 64, dens, 300, 300, 300)
+    print(f"direct 4K: oracle composite at {xs.size} pixels", flush=True)
+    ref = _oracle_nodes(oracle, proj, order, cfg, xs, ys)
+    err, masked = best_variant_error(out[ys, xs], ref)
+    report("direct_scene_3840x2160_t64_sampled", summarize(err, masked, ref["out"][:, :3]))
+    assert_within(err, masked)
+
+
+def test_tile_sizes_agree(torch_mod, oracle):
+    """List tiles 8, 16, 32 and 64 walk the same fragment sequence per pixel;
+    only the FP32 rounding of tile-relative means differs, which can settle a
+    near-tie decision the other way.  Every pixel where two tile sizes differ
+    by more than 1e-6 is composited by the oracle: each tile size's value
+    there must be one of the oracle's correct results."""
     torch = torch_mod
     from paper_2503_14171_amd import scenes
     from paper_2503_14171_amd.render import Renderer
     sc = scenes.make_scene("clusters", 200000, 31, 3)
     cam = scenes.make_camera(960, 540)
     rd = Renderer(sc)
+    tiles = (8, 16, 32, 64)
     outs = []
-    for tile in (8, 16, 32, 64):
+    for tile in tiles:
         print(f"tile agreement tile={tile}", flush=True)
-        outs.append(rd.render(cam, scenes.render_config(3, tile_size=tile)).cpu().numpy())
+        outs.append(rd.render(cam, scenes.render_config(3, tile_size=tile)).cpu().numpy().reshape(-1, 12))
+    diff = np.zeros(outs[0].shape[0], bool)
     for other in outs[1:]:
-        d = np.abs(outs[0] - other).max(-1)
-        # identical fragment sequences; only the FP32 rounding of tile-relative
-        # means differs (which can settle a rare near tie the other way)
-        assert np.quantile(d, 0.999) < 1e-5 and (d > 1e-4).mean() < 1e-3
+        diff |= np.abs(outs[0] - other).max(-1) > 1e-6
+    pix = np.nonzero(diff)[0]
+    print(f"tile agreement: {pix.size} pixels differ by more than 1e-6", flush=True)
+    assert pix.size <= 2000  # rare by construction (near ties only)
+    if pix.size == 0:
+        return
+    cfg = scenes.render_config(3, tile_size=16)
+    proj = oracle.project(sc, cam, cfg)
+    order = oracle.depth_order(proj)
+    ref = _oracle_nodes(oracle, proj, order, cfg, pix % 960, pix // 960)
+    for tile, o in zip(tiles, outs):
+        err, masked = best_variant_error(o[pix], ref)
+        report(f"tile_agreement_t{tile}_differing_pixels", summarize(err, masked, ref["out"]))
+        assert masked.sum() <= 1e-3 * o.shape[0]
+        assert_within(err, masked, max_masked_frac=1.0)
 
 
 @pytest.mark.parametrize("depth", [2, 3])
@@ -261,7 +414,8 @@ def test_frames_in_flight_recover_from_pair_overflow(torch_mod):
 def test_scene_x4_three_in_flight_equals_serial(torch_mod):
     """The benchmark's launch configuration (3M-Gaussian scene, 960x540 with
     derivatives, x4 to 3840x2160, 32x32 list tiles, three frames in flight)
-    gives, bit for bit, the serial frame that the sampled oracle test checks."""
+    gives, bit for bit, the serial frame at the same list tile, which
+    test_e2e_scene_x4_full_size_sampled checks against the oracle."""
     torch = torch_mod
     from paper_2503_14171_amd import scenes
     from paper_2503_14171_amd.render import FramePipeline, Renderer

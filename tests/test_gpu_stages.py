@@ -315,6 +315,43 @@ def test_raster_stage_tiny(gs, oracle, tile, want_grads):
     np.testing.assert_array_equal(nb[clean], ref["n_blend"][clean])
 
 
+@pytest.mark.parametrize("tile", [8, 32])
+def test_fragment_counts(gs, oracle, tile):
+    """gs_raster_fragment_counts (the benchmark's work counters): the image
+    equals gs_raster_grad's bit for bit; the blended count equals the
+    oracle's per pixel; every pixel evaluates at least the fragments it
+    blends and at most its tile list up to where it stopped."""
+    import torch
+    from paper_2503_14171_amd import scenes
+    sc = scenes.workload_scene("tiny")
+    cam = scenes.workload_camera("tiny")
+    cfg = scenes.render_config(0, tile_size=tile)
+    print(f"fragment counts tile={tile}", flush=True)
+    g, nb, ref = _raster_stage(gs, oracle, sc, cam, cfg, True)
+    pr = oracle.project(sc, cam, cfg)
+    rec = splat_records(pr, cfg)
+    rect = oracle.tile_rects(pr, cam["width"], cam["height"], tile)
+    d32 = np.where(pr["valid"], pr["depth"], np.inf).astype(np.float32)
+    tx, ty = _tiles_xy(cam, tile)
+    ids, ranges = oracle.tile_lists(d32, rect, tx, ty)
+    H, W = cam["height"], cam["width"]
+    out = torch.full((H * W, 12), np.nan, dtype=torch.float32, device="cuda")
+    nev = torch.full((H * W,), -1, dtype=torch.int32, device="cuda")
+    nbl = torch.full((H * W,), -1, dtype=torch.int32, device="cuda")
+    gs.gs_raster_fragment_counts(_dev(rec), _dev(ids), _dev(ranges), [cam], cfg, True, out, nev, nbl)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), g)
+    nev, nbl = nev.cpu().numpy(), nbl.cpu().numpy()
+    np.testing.assert_array_equal(nbl, nb)
+    clean = ref["n_amb"] == 0
+    np.testing.assert_array_equal(nbl[clean], ref["n_blend"][clean])
+    yy, xx = np.divmod(np.arange(H * W), W)
+    t = (yy // tile) * tx + xx // tile
+    list_len = ranges[t, 1] - ranges[t, 0]
+    assert (nev >= nbl).all() and (nev <= list_len).all()
+    assert nev.sum() > nbl.sum() > 0
+
+
 @pytest.mark.parametrize("tile", [16, 32, 64])
 def test_raster_stage_ragged_bg_opaque(gs, oracle, tile):
     """Image size not a multiple of the tile, non-zero background, opaque

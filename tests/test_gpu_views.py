@@ -119,7 +119,7 @@ def test_views_against_oracle(torch_mod, oracle):
         ref = oracle.composite(proj, order, cfg, xs.astype(float), ys.astype(float), variants=True)
         err, masked = best_variant_error(lows[v].cpu().numpy()[ys, xs], ref)
         report(f"views_oracle_view{v}", summarize(err, masked, ref["out"]))
-        assert_within(err, masked, max_masked_frac=2e-2)
+        assert_within(err, masked)
 
 
 def test_graph_replays_match_eager(torch_mod):
