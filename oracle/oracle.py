@@ -36,6 +36,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gsoracle.c")
 _LIB = os.path.join(_HERE, "libgsoracle.so")
+# GS_ORACLE_SANITIZE=1 builds and loads a copy instrumented with AddressSanitizer
+# and UndefinedBehaviorSanitizer (the process must preload their runtimes)
+_SANITIZE = os.environ.get("GS_ORACLE_SANITIZE") == "1"
+if _SANITIZE:
+    _LIB = os.path.join(_HERE, "libgsoracle_san.so")
 
 # Relative margins inside which a threshold decision counts as a near tie
 # (several outcomes are then correct, see ``composite``).
@@ -49,6 +54,9 @@ def build(force: bool = False) -> str:
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        if _SANITIZE:
+            cmd[1:1] = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                        "-fno-sanitize-recover=undefined"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
