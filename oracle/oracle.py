@@ -45,7 +45,7 @@ if _SANITIZE:
 # Relative margins inside which a threshold decision counts as a near tie
 # (several outcomes are then correct, see ``composite``).
 TIE_ALPHA = 2e-5
-TIE_T = 1e-3
+TIE_T = 1e-4
 
 
 def build(force: bool = False) -> str:
