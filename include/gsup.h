@@ -168,6 +168,28 @@ gs_status gs_bin_sort_async(int64_t n, const float* depth, const int32_t* rect,
                             int32_t* sorted_ids, int32_t* tile_ranges, int64_t* n_pairs_dev,
                             void* workspace, size_t workspace_bytes, void* stream);
 
+/* Bytes of the static device scratch gs_bin_sort_async_static works in. */
+#define GS_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* gs_bin_sort_async_static -- gs_bin_sort_async for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): no workspace argument; the library's
+ * own static scratch of GS_STATIC_SCRATCH_BYTES per GPU (held from the first
+ * call on that GPU to the end of the process) takes its place.  Same inputs,
+ * outputs, overflow rule and results as gs_bin_sort_async.  Sizes whose
+ * workspace, gs_bin_sort_workspace_size(n, capacity, ..), exceeds the scratch
+ * (e.g. more than 500k splats with 4M pairs) are rejected with
+ * GS_ERR_INVALID_ARGUMENT before anything is enqueued.  The call allocates
+ * nothing: the scratch's device address is looked up once per device, on the
+ * first call there.  Every call on one GPU shares that scratch, so calls that
+ * overlap on one GPU (other streams, other host threads) race and give
+ * undefined results; calls on one stream are ordered and safe.  Nothing in
+ * the scratch needs to start at zero: every pass writes what it later reads. */
+gs_status gs_bin_sort_async_static(int64_t n, const float* depth, const int32_t* rect,
+                                   const gs_camera* cam, const gs_raster_cfg* cfg,
+                                   int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
+                                   int64_t* n_pairs_dev, void* stream);
+
 /* gs_raster_grad -- front-to-back alpha blending of every pixel's tile list,
  * with the analytical screen-space derivatives of the blended colour.
  * Follows Sec. "Image Gradient Based Upscaling" (3DGS image gradients: the

@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
         L.gs_bin_sort_views.restype = ctypes.c_int
         L.gs_raster_grad_views.argtypes = [P, P, P, i32, cams_p, cfg_p, i32, P, P, P]
         L.gs_raster_grad_views.restype = ctypes.c_int
+        L.gs_bin_sort_async_static.argtypes = [i64, P, P, cam_p, cfg_p, i64, P, P, P, P]
+        L.gs_bin_sort_async_static.restype = ctypes.c_int
         L.gs_raster_fragment_counts.argtypes = [P, P, P, i32, cams_p, cfg_p, i32, P, P, P, P]
         L.gs_raster_fragment_counts.restype = ctypes.c_int
         L.gs_upscale_hermite_views.argtypes = [P, i32, ctypes.POINTER(i32), P, ctypes.POINTER(i32), i32, P]
@@ -226,6 +228,15 @@ def gs_bin_sort_async(n: int, depth, rect, cam: dict, cfg: dict, capacity: int, 
                                    _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
                                    _ptr(n_pairs_dev, torch.int64), _ptr(workspace, torch.uint8),
                                    workspace.numel(), _stream(stream)))
+
+
+def gs_bin_sort_async_static(n: int, depth, rect, cam: dict, cfg: dict, capacity: int, sorted_ids,
+                             tile_ranges, n_pairs_dev, stream=None) -> None:
+    """gs_bin_sort_async in the library's static scratch (no workspace, no allocation)."""
+    _check(lib().gs_bin_sort_async_static(n, _ptr(depth, torch.float32), _ptr(rect, torch.int32),
+                                          ctypes.byref(camera(cam)), ctypes.byref(raster_cfg(cfg)), capacity,
+                                          _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
+                                          _ptr(n_pairs_dev, torch.int64), _stream(stream)))
 
 
 # ---- batched views ---------------------------------------------------------

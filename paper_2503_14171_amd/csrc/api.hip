@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "gsup_internal.h"
 
@@ -85,6 +86,36 @@ int64_t total_pixels(int32_t nv, const gs_camera* cams) {
   int64_t t = 0;
   for (int v = 0; v < nv; ++v) t += (int64_t)cams[v].width * cams[v].height;
   return t;
+}
+
+// Bin/sort scratch of gs_bin_sort_async_static: a device array that every
+// GPU the library runs on holds from the code object's load to the end of
+// the process.  Host code never uses the array's name as an address (on the
+// host it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+__device__ __align__(256) unsigned char scratch[GS_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+gs_status static_scratch(const char* fn, void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(e, fn);
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(GS_ERR_UNSUPPORTED, "%s: device %d beyond the %d the library tracks", fn, dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return check_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(GS_ERR_HIP, "%s: no device address for the static scratch", fn);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
 }
 
 }  // namespace
@@ -285,6 +316,27 @@ gs_status gs_bin_sort_async(int64_t n, const float* depth, const int32_t* rect,
   if (!n_pairs_dev) return fail(GS_ERR_INVALID_ARGUMENT, "gs_bin_sort_async: n_pairs_dev is NULL");
   return bin_sort_impl("gs_bin_sort_async", n, 1, cam, cfg, depth, rect, capacity, sorted_ids,
                        tile_ranges, nullptr, n_pairs_dev, workspace, workspace_bytes, stream);
+}
+
+gs_status gs_bin_sort_async_static(int64_t n, const float* depth, const int32_t* rect,
+                                   const gs_camera* cam, const gs_raster_cfg* cfg,
+                                   int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
+                                   int64_t* n_pairs_dev, void* stream) {
+  g_msg[0] = 0;
+  const char* fn = "gs_bin_sort_async_static";
+  if (!n_pairs_dev) return fail(GS_ERR_INVALID_ARGUMENT, "%s: n_pairs_dev is NULL", fn);
+  // sizes first, on the host (0: the settings are invalid, which the common
+  // validation below reports)
+  const size_t need = bin_sort_ws(n, 1, cam, cfg, capacity);
+  if (need > (size_t)GS_STATIC_SCRATCH_BYTES)
+    return fail(GS_ERR_INVALID_ARGUMENT,
+                "%s: %lld splats and capacity %lld need %zu bytes of scratch; the static scratch "
+                "holds %zu (gs_bin_sort_async takes a workspace of any size)",
+                fn, (long long)n, (long long)capacity, need, (size_t)GS_STATIC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if (need > 0) GS_CHECK(static_scratch(fn, &ws));
+  return bin_sort_impl(fn, n, 1, cam, cfg, depth, rect, capacity, sorted_ids, tile_ranges,
+                       nullptr, n_pairs_dev, ws, (size_t)GS_STATIC_SCRATCH_BYTES, stream);
 }
 
 gs_status gs_raster_grad(const gs_splat* splats, const int32_t* sorted_ids,

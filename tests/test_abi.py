@@ -119,6 +119,12 @@ def test_validation_rejects_bad_calls(L):
     assert "workspace" in lib.gs_last_error_message().decode()
     assert lib.gs_bin_sort(10, F, F, R(cam), R(cfg), -5, F, F, R(k), F, ws, None) == L.GS_ERR_INVALID_ARGUMENT
     assert lib.gs_bin_sort(10, F, F, R(cam), R(cfg), 100, F, F, None, F, ws, None) == L.GS_ERR_INVALID_ARGUMENT
+    # the scratch-free bin sort: a device counter is required, and sizes beyond
+    # its static scratch are refused on the host, before any device call
+    assert lib.gs_bin_sort_async_static(10, F, F, R(cam), R(cfg), 100, F, F, None, None) == L.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_bin_sort_async_static(10, F, F, R(cam), R(cfg), 8_000_000, F, F, F,
+                                        None) == L.GS_ERR_INVALID_ARGUMENT
+    assert "static scratch" in lib.gs_last_error_message().decode()
     assert lib.gs_upscale_hermite(F, 1, 5, ctypes.c_void_p(1 << 20), 4, 10, None) == L.GS_ERR_INVALID_ARGUMENT
     assert lib.gs_upscale_hermite(F, 4, 5, ctypes.c_void_p(1 << 20), 3, 10, None) == L.GS_ERR_INVALID_ARGUMENT
     assert lib.gs_upscale_hermite(F, 4, 5, ctypes.c_void_p(4096 + 64), 8, 10, None) == L.GS_ERR_INVALID_ARGUMENT
