@@ -8,11 +8,13 @@
 //      depth bits (stable LSD radix sort, so equal depths keep index order;
 //      the first pass drops the +inf depths of splats without tiles and the
 //      top pass runs only for depth ranges wider than 8 binades),
-//   2. sums the splats' tile counts per block of 256 splats in that order
-//      (their clipped rectangles travel through the sort packed in 32 bits;
-//      one small scan gives every block's pair offset and the total K),
-//   3. emits (tile, splat) pairs in depth order, one thread per pair, and
-//   4. stably sorts the pairs by tile id only (ceil(log2 T) bits),
+//   2. sums the splats' tile counts per block of 4096 splats in that order
+//      (their clipped rectangles travel through the sort packed in 32 bits),
+//   3. emits (tile, splat) pairs in depth order, one thread per pair, every
+//      block of 256 splats finding its first pair and the total K from those
+//      sums itself (no separate scan launch), and
+//   4. stably sorts the pairs by tile id only (ceil(log2 T) bits; with one
+//      pass, its digit counts are the tile ranges),
 // which yields each tile's list in (depth, index) order while moving the
 // large pair array only once or twice with 8-byte records.
 //
@@ -117,43 +119,6 @@ __device__ __forceinline__ T block_scan_inplace(T* __restrict__ data, int64_t m,
   return carry;
 }
 
-template <typename T>
-__device__ __forceinline__ void load_blocked(const T* in, int64_t m, int64_t base, T (&v)[kItems]) {
-  const int64_t s = base + (int64_t)threadIdx.x * kItems;
-#pragma unroll
-  for (int k = 0; k < kItems; ++k) v[k] = (s + k < m) ? in[s + k] : T(0);
-}
-
-// Exclusive scan of m elements in one workgroup of 1024 threads (chunks of
-// 16384, kItems consecutive elements per thread, with a carry); writes the
-// grand total.  For the short arrays of per-block sums (on MI355X the
-// blocked layout measured faster here than the striped one above).
-constexpr int kSmallThreads = 1024;
-template <typename T>
-__global__ __launch_bounds__(kSmallThreads) void scan_small_kernel(T* __restrict__ data, int64_t m,
-                                                                   T* __restrict__ total) {
-  __shared__ T s_w[kSmallThreads / 64];
-  T carry = 0;
-  for (int64_t base = 0; base < m; base += (int64_t)kSmallThreads * kItems) {
-    T v[kItems];
-    load_blocked(data, m, base, v);
-    T sum = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) sum += v[k];
-    T excl;
-    const T tot = block_exclusive_scan<T, kSmallThreads>(sum, &excl, s_w);
-    T run = carry + excl;
-    const int64_t s0 = base + (int64_t)threadIdx.x * kItems;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      if (s0 + k < m) data[s0 + k] = run;
-      run += v[k];
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0) *total = carry;
-}
-
 // ----------------------------------------------------------------------------
 // tile rectangles
 // ----------------------------------------------------------------------------
@@ -238,6 +203,40 @@ static_assert(kMaxDigitBits >= 1 && kMaxDigitBits <= 11, "digit width");
 constexpr int kMaxTileDigitBits = GSUP_MAX_TILE_DIGIT_BITS;
 constexpr int kMaxAnyDigitBits = kMaxDigitBits > kMaxTileDigitBits ? kMaxDigitBits : kMaxTileDigitBits;
 static_assert(kMaxTileDigitBits >= 1 && kMaxTileDigitBits <= 11, "tile digit width");
+
+// Tile ranges from per-tile pair counts (tiles <= 2^kMaxAnyDigitBits): an
+// exclusive scan by one workgroup; a tile without pairs gets [0, 0).  Run by
+// block 0 of a single-pass tile sort's downsweep, whose digit counts are the
+// list lengths.
+struct RangesOut {
+  int32_t* ranges = nullptr;
+  int64_t tiles = 0;
+};
+
+__device__ __forceinline__ void ranges_from_counts(const uint32_t* __restrict__ counts,
+                                                   const RangesOut& ro, uint32_t* s_w) {
+  constexpr int R = 1 << kMaxAnyDigitBits;
+  constexpr int DPT = R > kThreads ? R / kThreads : 1;
+  uint32_t v[DPT], sum = 0;
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int64_t t = (int64_t)threadIdx.x * DPT + k;
+    v[k] = t < ro.tiles ? counts[t] : 0u;
+    sum += v[k];
+  }
+  uint32_t excl;
+  block_exclusive_scan<uint32_t>(sum, &excl, s_w);
+#pragma unroll
+  for (int k = 0; k < DPT; ++k) {
+    const int64_t t = (int64_t)threadIdx.x * DPT + k;
+    if (t < ro.tiles) {
+      ro.ranges[2 * t] = v[k] ? (int32_t)excl : 0;
+      ro.ranges[2 * t + 1] = v[k] ? (int32_t)(excl + v[k]) : 0;
+    }
+    excl += v[k];
+  }
+}
+
 
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -424,9 +423,14 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in /* null: index */,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t m,
     const uint64_t* m_dev, int64_t cap, int shift, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ totals, int64_t nblocks, DepthKeys dk, Payload pl) {
+    const uint32_t* __restrict__ totals, int64_t nblocks, DepthKeys dk, Payload pl,
+    RangesOut ro) {
   constexpr int R = 1 << BITS;
+  __shared__ uint32_t s_w[kWaves];
   if (pass_is_identity(dk, shift)) return;
+  // a single-pass tile sort: its digit counts are the list lengths (written
+  // also when the pair list is empty)
+  if (ro.ranges && blockIdx.x == 0) ranges_from_counts(totals, ro, s_w);
   if (m_dev) m = eff_count(m_dev, cap);
   if ((int64_t)blockIdx.x * kTile >= m) return;
   if (dk.info && blockIdx.x == 0 && threadIdx.x == 0) dk.info[2] = (uint32_t)dk.out_index;
@@ -436,7 +440,6 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   __shared__ uint32_t s_wh[kWaves][R];  // per-wave digit counts, then per-wave bases
   __shared__ uint32_t s_gbase[R];
   __shared__ uint32_t s_lstart[R];
-  __shared__ uint32_t s_w[kWaves];
   __shared__ uint32_t s_count;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -577,7 +580,7 @@ template <int BITS>
 hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                            uint32_t* vout, int64_t m, const uint64_t* m_dev, int shift,
                            uint32_t* hist, uint32_t* totals, const DepthKeys& dk,
-                           const Payload& pl, hipStream_t stream) {
+                           const Payload& pl, const RangesOut& ro, hipStream_t stream) {
   const int64_t nb = std::max<int64_t>(ceil_div(m, kTile), 1);
   radix_upsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(kin, m, m_dev, m, shift, hist,
                                                                      nb, dk);
@@ -587,7 +590,7 @@ hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* k
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   radix_downsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(
-      kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb, dk, pl);
+      kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb, dk, pl, ro);
   return hipGetLastError();
 }
 
@@ -595,13 +598,13 @@ hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* k
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       int64_t m, const uint64_t* m_dev, int shift, int bits, uint32_t* hist,
                       uint32_t* totals, const DepthKeys& dk, const Payload& pl,
-                      hipStream_t stream) {
+                      const RangesOut& ro, hipStream_t stream) {
   switch (bits) {
 #define GS_RADIX_CASE(B)                                                                  \
   case B:                                                                                 \
     if (B <= kMaxAnyDigitBits)                                                            \
       return radix_pass_bits<(B <= kMaxAnyDigitBits ? B : 1)>(kin, vin, kout, vout, m, m_dev, \
-                                                           shift, hist, totals, dk, pl, stream); \
+                                                           shift, hist, totals, dk, pl, ro, stream); \
     break;
     GS_RADIX_CASE(1)
     GS_RADIX_CASE(2)
@@ -651,9 +654,25 @@ int depth_plan(int widths[8]) {
 #endif
 constexpr int kEmit = GSUP_EMIT_BLOCK;  // splats per count / emit block
 
-// Per block of kEmit splats in depth order, the sum of their tile counts.
-// The depth sort left only the splats with a finite depth (kept[0] of them)
-// in the order and packed-rectangle buffers its last pass wrote (dinfo[2]).
+constexpr int kCountPer = 16;                // splats per thread of the count kernel
+constexpr int kCount = kEmit * kCountPer;     // splats per count block
+constexpr int kSubs = kCount / kEmit;         // emit blocks per count block
+static_assert(kCount % kEmit == 0 && kCountPer % 4 == 0, "count / emit blocking");
+
+// Tile count of depth-order position p (the depth sort left only the splats
+// with a finite depth, kept[0] of them, in the order and packed-rectangle
+// buffers its last pass wrote).
+__device__ __forceinline__ uint32_t pair_count_at(int64_t p, uint32_t code,
+                                                  const uint32_t* __restrict__ order,
+                                                  const int4* __restrict__ rect,
+                                                  const ViewTiles& vt) {
+  const uint32_t e = code == kRectEscape ? order[p] : 0u;
+  return rect_tiles(splat_rect(code, e, rect, vt));
+}
+
+// Pair counts in depth order, per block of kCount splats (thread t sums
+// kCountPer consecutive ones): sub[16 b + k] = pairs of this block before its
+// k-th run of kEmit splats (an emit block), blk[b] = the block's pairs.
 __global__ __launch_bounds__(kEmit) void pair_count_kernel(int64_t n,
                                                            const uint32_t* __restrict__ order0,
                                                            const uint32_t* __restrict__ order1,
@@ -663,29 +682,45 @@ __global__ __launch_bounds__(kEmit) void pair_count_kernel(int64_t n,
                                                            const uint64_t* kept,
                                                            const int4* __restrict__ rect,
                                                            ViewTiles vt,
-                                                           uint64_t* __restrict__ bsum) {
+                                                           uint64_t* __restrict__ sub,
+                                                           uint64_t* __restrict__ blk) {
   __shared__ uint64_t s_w[kEmit / 64];
   const int64_t nk = eff_count(kept, n);
   const bool second = dinfo[2] != 0u;
-  const int64_t p = (int64_t)blockIdx.x * kEmit + threadIdx.x;
+  const uint32_t* __restrict__ order = second ? order1 : order0;
+  const uint32_t* __restrict__ prect = second ? prect1 : prect0;
+  const int64_t p0 = (int64_t)blockIdx.x * kCount + (int64_t)threadIdx.x * kCountPer;
   uint64_t c = 0;
-  if (p < nk) {
-    const uint32_t code = (second ? prect1 : prect0)[p];
-    const uint32_t e = code == kRectEscape ? (second ? order1 : order0)[p] : 0u;
-    c = rect_tiles(splat_rect(code, e, rect, vt));
+  if (p0 + kCountPer <= nk) {  // whole run: 16-byte loads (p0 is a multiple of 16)
+    const uint4* q = reinterpret_cast<const uint4*>(prect + p0);
+#pragma unroll
+    for (int k = 0; k < kCountPer / 4; ++k) {
+      const uint4 v = q[k];
+      c += pair_count_at(p0 + 4 * k, v.x, order, rect, vt);
+      c += pair_count_at(p0 + 4 * k + 1, v.y, order, rect, vt);
+      c += pair_count_at(p0 + 4 * k + 2, v.z, order, rect, vt);
+      c += pair_count_at(p0 + 4 * k + 3, v.w, order, rect, vt);
+    }
+  } else {
+    for (int k = 0; k < kCountPer; ++k)
+      if (p0 + k < nk) c += pair_count_at(p0 + k, prect[p0 + k], order, rect, vt);
   }
   uint64_t excl;
   const uint64_t tot = block_exclusive_scan<uint64_t, kEmit>(c, &excl, s_w);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+  constexpr int kThreadsPerSub = kEmit / kSubs;
+  if (threadIdx.x % kThreadsPerSub == 0)
+    sub[(int64_t)blockIdx.x * kSubs + threadIdx.x / kThreadsPerSub] = excl;
+  if (threadIdx.x == 0) blk[blockIdx.x] = tot;
 }
 
 // Pair emission, load-balanced: a block takes kEmit consecutive splats (depth
-// order), whose pairs form one contiguous range starting at boff[block]; the
-// block scans its splats' tile counts in LDS, then every thread writes one
-// pair per step, finding its splat by binary search over those offsets, so
-// the writes are coalesced whatever the splats' tile counts.  Tile keys are
-// global: view v's tiles are numbered from tile_off[v].  With `total` set
-// (device-side count) nothing is written unless the total fits `cap`.
+// order), whose pairs form one contiguous range; it finds where that range
+// starts (and the total K) from the count kernel's sums itself, scans its
+// splats' tile counts in LDS, then every thread writes one pair per step,
+// finding its splat by binary search over those offsets, so the writes are
+// coalesced whatever the splats' tile counts.  Tile keys are global: view
+// v's tiles are numbered from tile_off[v].  Block 0 writes K to `total`;
+// nothing is written when K exceeds `cap` (or the int32 index range).
 __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* __restrict__ order0,
                                                      const uint32_t* __restrict__ order1,
                                                      const uint32_t* __restrict__ prect0,
@@ -693,16 +728,46 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
                                                      const uint32_t* __restrict__ dinfo,
                                                      const uint64_t* kept,
                                                      const int4* __restrict__ rect,
-                                                     const uint64_t* __restrict__ boff,
-                                                     ViewTiles vt, const uint64_t* total,
-                                                     int64_t cap, uint32_t* __restrict__ tkeys,
+                                                     const uint64_t* __restrict__ sub,
+                                                     const uint64_t* __restrict__ blk,
+                                                     int64_t nblk, ViewTiles vt,
+                                                     uint64_t* __restrict__ total, int64_t cap,
+                                                     uint32_t* __restrict__ tkeys,
                                                      uint32_t* __restrict__ tvals) {
-  if (total && eff_count(total, cap) == 0) return;
   __shared__ uint32_t s_off[kEmit + 1];
   __shared__ int4 s_rect[kEmit];
   __shared__ uint32_t s_gid[kEmit];
   __shared__ uint32_t s_w[kEmit / 64];
+  __shared__ uint64_t s_a[kEmit / 64], s_p[kEmit / 64];
   const int t = threadIdx.x;
+  // K and this block's first pair: sums over the count blocks
+  const int64_t cb = (int64_t)blockIdx.x / kSubs;
+  uint64_t all = 0, pre = 0;
+  for (int64_t b = t; b < nblk; b += kEmit) {
+    const uint64_t v = blk[b];
+    all += v;
+    pre += b < cb ? v : 0;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    all += __shfl_xor(all, d, 64);
+    pre += __shfl_xor(pre, d, 64);
+  }
+  if ((t & 63) == 0) {
+    s_a[t >> 6] = all;
+    s_p[t >> 6] = pre;
+  }
+  __syncthreads();
+  all = 0;
+  pre = 0;
+#pragma unroll
+  for (int w = 0; w < kEmit / 64; ++w) {
+    all += s_a[w];
+    pre += s_p[w];
+  }
+  if (blockIdx.x == 0 && t == 0) *total = all;
+  if (all > (uint64_t)cap || all >= (uint64_t(1) << 31)) return;  // uniform over the block
+  const uint64_t base = pre + sub[blockIdx.x];
   const int64_t nk = eff_count(kept, n);
   const bool second = dinfo[2] != 0u;
   const uint32_t* __restrict__ order = second ? order1 : order0;
@@ -723,7 +788,6 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
   s_off[t] = excl;
   if (t == 0) s_off[nb] = tot;
   __syncthreads();
-  const uint64_t base = boff[blockIdx.x];
   for (uint32_t k = t; k < tot; k += kEmit) {
     // owner: the last j with s_off[j] <= k (splats without tiles have s_off[j] == s_off[j+1])
     int lo = 0, hi = nb;  // invariant: s_off[lo] <= k < s_off[hi]
@@ -776,33 +840,6 @@ __global__ __launch_bounds__(kThreads) void tile_range_kernel(int64_t K, const u
   }
 }
 
-// Tile ranges from per-tile pair counts (tiles <= 2^kMaxAnyDigitBits): an
-// exclusive scan in one workgroup; a tile without pairs gets [0, 0).
-__global__ __launch_bounds__(kThreads) void ranges_from_counts_kernel(
-    const uint32_t* __restrict__ counts, int64_t tiles, int32_t* __restrict__ ranges) {
-  constexpr int R = 1 << kMaxAnyDigitBits;
-  constexpr int DPT = R > kThreads ? R / kThreads : 1;
-  __shared__ uint32_t s_w[kWaves];
-  uint32_t v[DPT], sum = 0;
-#pragma unroll
-  for (int k = 0; k < DPT; ++k) {
-    const int64_t t = (int64_t)threadIdx.x * DPT + k;
-    v[k] = t < tiles ? counts[t] : 0u;
-    sum += v[k];
-  }
-  uint32_t excl;
-  block_exclusive_scan<uint32_t>(sum, &excl, s_w);
-#pragma unroll
-  for (int k = 0; k < DPT; ++k) {
-    const int64_t t = (int64_t)threadIdx.x * DPT + k;
-    if (t < tiles) {
-      ranges[2 * t] = v[k] ? (int32_t)excl : 0;
-      ranges[2 * t + 1] = v[k] ? (int32_t)(excl + v[k]) : 0;
-    }
-    excl += v[k];
-  }
-}
-
 inline unsigned grid1d(int64_t n, int threads) { return (unsigned)ceil_div(n, threads); }
 
 }  // namespace
@@ -844,7 +881,8 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles) {
   p.off_gkey[1] = take(n4);
   p.off_gval[0] = take(n4);
   p.off_gval[1] = take(n4);
-  p.off_bsum = take(sizeof(uint64_t) * (size_t)ceil_div(n1, kEmit));
+  p.off_bsum = take(sizeof(uint64_t) * (size_t)ceil_div(n1, kCount) * kSubs);
+  p.off_bblk = take(sizeof(uint64_t) * (size_t)ceil_div(n1, kCount));
   p.off_prect[0] = take(n4);
   p.off_prect[1] = take(n4);
   p.off_pkey[0] = take(c4);
@@ -868,6 +906,7 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   char* ws = static_cast<char*>(workspace);
   auto u32 = [&](size_t o) { return reinterpret_cast<uint32_t*>(ws + o); };
   uint64_t* bsum = reinterpret_cast<uint64_t*>(ws + p.off_bsum);
+  uint64_t* bblk = reinterpret_cast<uint64_t*>(ws + p.off_bblk);
   uint32_t* hist = u32(p.off_hist);
   uint32_t* totals = u32(p.off_totals);
   // device-count mode: the total goes straight to the caller's counter
@@ -921,7 +960,7 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     pl.to = u32(p.off_prect[cur ^ 1]);
     GS_TRY(radix_pass(kin, vin, u32(p.off_gkey[cur ^ 1]), u32(p.off_gval[cur ^ 1]), n,
                       k == 0 ? nullptr : kept_count, shift, widths[k], hist, totals, dk, pl,
-                      stream),
+                      RangesOut{}, stream),
            "depth radix pass");
     shift += widths[k];
     cur ^= 1;
@@ -931,13 +970,25 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   const uint32_t* prect0 = u32(p.off_prect[0]);
   const uint32_t* prect1 = u32(p.off_prect[1]);
 
-  // 2. tile counts in depth order, pair offsets per block of splats, total K
-  const int64_t nbe = ceil_div(n, kEmit);
-  pair_count_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, prect0, prect1, dinfo,
-                                                          kept_count, r4, vt, bsum);
+  // 2. tile counts in depth order per block of splats; 3. pairs in depth
+  //    order, each emit block finding its offset and the total K from those
+  //    sums (K goes to the caller's counter in device-count mode); nothing is
+  //    emitted when K exceeds the capacity
+  const int64_t nbc = ceil_div(n, kCount);
+  const int64_t nbe = nbc * kSubs;
+  pair_count_kernel<<<(unsigned)nbc, kEmit, 0, stream>>>(n, order0, order1, prect0, prect1, dinfo,
+                                                          kept_count, r4, vt, bsum, bblk);
   GS_TRY(hipGetLastError(), "pair_count_kernel");
-  scan_small_kernel<uint64_t><<<1, kSmallThreads, 0, stream>>>(bsum, nbe, total);
-  GS_TRY(hipGetLastError(), "pair offset scan");
+  const int passes = radix_plan(p.tile_bits, widths, kMaxTileDigitBits);
+  // values end in sorted_ids after `passes` ping-pong steps
+  uint32_t* vbuf[2];
+  vbuf[0] = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(sorted_ids) : u32(p.off_pval);
+  vbuf[1] = (passes % 2 == 0) ? u32(p.off_pval) : reinterpret_cast<uint32_t*>(sorted_ids);
+  uint32_t* kbuf[2] = {u32(p.off_pkey[0]), u32(p.off_pkey[1])};
+  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, prect0, prect1, dinfo,
+                                                   kept_count, r4, bsum, bblk, nbc, vt, total,
+                                                   p.capacity, kbuf[0], vbuf[0]);
+  GS_TRY(hipGetLastError(), "emit_kernel");
   int64_t m = p.capacity;  // device-count mode: grids sized by the capacity
   if (!dev) {
     uint64_t K = 0;
@@ -953,21 +1004,13 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     m = (int64_t)K;
   }
   const uint64_t* m_dev = dev ? total : nullptr;
-
-  // 3. empty ranges, then pairs in depth order
-  fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
-  GS_TRY(hipGetLastError(), "fill_i32_kernel");
+  // the ranges start empty unless a single tile pass writes every tile's
+  // range from its digit counts anyway
+  if (m == 0 || passes > 1) {
+    fill_i32_kernel<<<grid1d(2 * p.tiles, 256), 256, 0, stream>>>(tile_ranges, 2 * p.tiles, 0);
+    GS_TRY(hipGetLastError(), "fill_i32_kernel");
+  }
   if (m == 0) return GS_OK;
-  const int passes = radix_plan(p.tile_bits, widths, kMaxTileDigitBits);
-  // values end in sorted_ids after `passes` ping-pong steps
-  uint32_t* vbuf[2];
-  vbuf[0] = (passes % 2 == 0) ? reinterpret_cast<uint32_t*>(sorted_ids) : u32(p.off_pval);
-  vbuf[1] = (passes % 2 == 0) ? u32(p.off_pval) : reinterpret_cast<uint32_t*>(sorted_ids);
-  uint32_t* kbuf[2] = {u32(p.off_pkey[0]), u32(p.off_pkey[1])};
-  emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, prect0, prect1, dinfo,
-                                                   kept_count, r4, bsum, vt, m_dev, p.capacity,
-                                                   kbuf[0], vbuf[0]);
-  GS_TRY(hipGetLastError(), "emit_kernel");
 
   // 4. stable sort of the pairs by tile id
   cur = 0;
@@ -975,18 +1018,20 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   for (int k = 0; k < passes; ++k) {
     // the keys of the last pass are only needed by tile_range_kernel
     uint32_t* kout = (k + 1 == passes && passes == 1) ? nullptr : kbuf[cur ^ 1];
+    // one pass: the digit of every pair is its whole tile id, so the pass's
+    // digit counts are the list lengths and their running sum the starts
+    RangesOut ro;
+    if (passes == 1) {
+      ro.ranges = tile_ranges;
+      ro.tiles = p.tiles;
+    }
     GS_TRY(radix_pass(kbuf[cur], vbuf[cur], kout, vbuf[cur ^ 1], m, m_dev, shift,
-                      widths[k], hist, totals, DepthKeys{}, Payload{}, stream),
+                      widths[k], hist, totals, DepthKeys{}, Payload{}, ro, stream),
            "tile radix pass");
     shift += widths[k];
     cur ^= 1;
   }
-  if (passes == 1) {
-    // one pass: the digit of every pair is its whole tile id, so the pass's
-    // digit counts are the list lengths and their running sum the starts
-    ranges_from_counts_kernel<<<1, kThreads, 0, stream>>>(totals, p.tiles, tile_ranges);
-    GS_TRY(hipGetLastError(), "ranges_from_counts_kernel");
-  } else {
+  if (passes > 1) {
     tile_range_kernel<<<(unsigned)ceil_div(m, kTile), kThreads, 0, stream>>>(m, m_dev, kbuf[cur],
                                                                              tile_ranges);
     GS_TRY(hipGetLastError(), "tile_range_kernel");

@@ -62,7 +62,8 @@ struct BinSortPlan {
   int tile_bits = 0;      // bits of the tile id key
   // workspace layout (byte offsets)
   size_t off_gkey[2], off_gval[2];  // depth keys / splat ids, ping-pong [n]
-  size_t off_bsum;                  // tile-count sums per block of splats -> pair offsets
+  size_t off_bsum;                  // pairs of a count block before each of its emit blocks
+  size_t off_bblk;                  // pairs per count block of splats
   size_t off_prect[2];              // packed clipped tile rectangles, ping-pong with the ids [n]
   size_t off_pkey[2];               // pair tile keys, ping-pong [capacity]
   size_t off_pval;                  // pair ids, second buffer [capacity]

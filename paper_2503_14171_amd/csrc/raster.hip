@@ -67,7 +67,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
   static_assert(BATCH >= 16 && BATCH <= NT, "one splat per staging thread");
   __shared__ float4 s_a[BATCH];  // mean x, mean y (tile-relative), conic a, conic b
   __shared__ float4 s_b[BATCH];  // conic c, log2 sigma, support, red
-  __shared__ float2 s_c[BATCH];  // green, blue
+  __shared__ float4 s_c[BATCH];  // green, blue (16-byte stride: one LDS address for all three)
   __shared__ uint32_t s_mask[NW > 1 ? BATCH : 1];                // quadrants a staged splat can reach
   __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];  // per-wave hits, batch order
 
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
       const float mx = (float)(m.x - ox), my = (float)(m.y - oy);
       s_a[t] = make_float4(mx, my, q.x, q.y);
       s_b[t] = make_float4(q.z, log2f(q.w), c.w, c.x);
-      s_c[t] = make_float2(c.y, c.z);
+      s_c[t] = make_float4(c.y, c.z, 0.f, 0.f);
       if (NW > 1) {
         // quadrants met by the box of {d^T Q d <= support}: half extents
         // sqrt(support Sigma'_xx), Sigma'_xx = c / (a c - b^2)
@@ -164,16 +164,18 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
           const float q = fmaf(dx, u, dy * v);        // d^T Q d
           if (AUX && !done) ++ne;
           if (!done && q <= gb.z) {                   // alpha >= alpha_min
-            const float2 gc = s_c[j];
+            const float4 gc = s_c[j];
             // the exponent is >= log2(alpha_min) > -126: no denormal handling needed
-            float alpha = __builtin_amdgcn_exp2f(fmaf(q, -kHalfLog2e, gb.y));
-            const bool clamp = alpha > p.alpha_max;
-            alpha = clamp ? p.alpha_max : alpha;
+            const float a0 = __builtin_amdgcn_exp2f(fmaf(q, -kHalfLog2e, gb.y));
+            // clamped at alpha_max with zero screen derivatives: sa scales them
+            const bool clamp = a0 > p.alpha_max;
+            const float alpha = clamp ? p.alpha_max : a0;
             const float w = T * alpha;
             if (GRAD) {
-              const float ax = clamp ? 0.f : -alpha * u;
-              const float ay = clamp ? 0.f : -alpha * v;
-              const float axy = clamp ? 0.f : alpha * fmaf(u, v, -ga.w);
+              const float sa = clamp ? 0.f : a0;
+              const float ax = -sa * u;
+              const float ay = -sa * v;
+              const float axy = sa * fmaf(u, v, -ga.w);
               const float kx = fmaf(T, ax, Tx * alpha);
               const float ky = fmaf(T, ay, Ty * alpha);
               const float kxy = fmaf(T, axy, fmaf(Tx, ay, fmaf(Ty, ax, Txy * alpha)));

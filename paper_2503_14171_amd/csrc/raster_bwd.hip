@@ -232,12 +232,14 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
       if (act) {
         const float4 gc = s_c[j];
         const float cr = gb.w, cg = gc.x, cb = gc.y, inv_sig = gc.z;
-        float alpha = __builtin_amdgcn_exp2f(fmaf(q, -kHalfLog2e, gb.y));
-        const bool clamp = alpha > p.alpha_max;
-        alpha = clamp ? p.alpha_max : alpha;
-        const float ax = clamp ? 0.f : -alpha * u;
-        const float ay = clamp ? 0.f : -alpha * v;
-        const float axy = clamp ? 0.f : alpha * fmaf(u, v, -ga.w);
+        const float a0 = __builtin_amdgcn_exp2f(fmaf(q, -kHalfLog2e, gb.y));
+        // the forward's clamp: alpha_max with zero screen derivatives
+        const bool clamp = a0 > p.alpha_max;
+        const float alpha = fminf(a0, p.alpha_max);
+        const float sa = clamp ? 0.f : a0;
+        const float ax = -sa * u;
+        const float ay = -sa * v;
+        const float axy = sa * fmaf(u, v, -ga.w);
         // state before this fragment (1 / (1 - alpha) by the hardware reciprocal:
         // 1 ulp, and 1 - alpha >= 1 - alpha_max is far from zero)
         const float om = __builtin_amdgcn_rcpf(1.f - alpha);
