@@ -105,6 +105,9 @@ def run_gpu(args):
     name, sx, sy = WORKLOADS[args.workload]
     sc = scenes.workload_scene(name)
     cam = scenes.workload_camera(name)
+    # a far plane at the scene's depth bound (it culls nothing) tells the
+    # depth sort how many digit passes the key range needs
+    cam["far_plane"] = scenes.depth_bound(sc, cam)
     cfg = scenes.render_config(sc["sh_degree"], tile_size=args.tile)
     w, h = cam["width"], cam["height"]
     W, H = round(w * sx), round(h * sy)
@@ -340,6 +343,7 @@ def run_gpu(args):
         per = []
         for k in range(8):
             cam_o = scenes.orbit_camera(w, h, 45.0 * k, 15.0)
+            cam_o["far_plane"] = scenes.depth_bound(sc, cam_o)
             cam_oh = scenes.scale_camera(cam_o, W, H)
             ms_up = frames(depth, n_o, 2, False, cam_o)[0]
             ms_d = min(time_direct(t, depth, cam_oh, n_o)[0] for t in (32, 64))

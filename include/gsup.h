@@ -70,6 +70,9 @@ typedef struct gs_camera {
   float view[12];        /* world -> camera [R | t_W], row-major */
   float cam_pos[3];      /* camera centre in world space (SH view direction) */
   float near_plane;      /* Gaussians with camera z <= near_plane are culled, > 0 */
+  float far_plane;       /* Gaussians with camera z > far_plane are culled; 0: no far plane.
+                            A far plane bounds the depth keys, so gs_bin_sort runs only the
+                            radix passes the range [near_plane, far_plane] needs */
 } gs_camera;
 
 /* Render settings.  The paper fixes none of these numbers; see each field. */
@@ -97,6 +100,10 @@ typedef struct gs_splat {
   float rgb[3];    /* view-dependent colour, max(0, sum_lm Y_lm k_lm + 1/2) */
   float support;   /* 2 ln(sigma / alpha_min): alpha >= alpha_min <=> d^T Q d <= support */
 } gs_splat;
+
+/* Pair count the asynchronous bin sorts report when a finite depth lies
+ * outside the cameras' [near_plane, far_plane] (see gs_camera.far_plane). */
+#define GS_PAIRS_DEPTH_RANGE (1ll << 62)
 
 /* Number of tiles of a width x height raster: ceil(W/ts) * ceil(H/ts). */
 int64_t gs_num_tiles(int32_t width, int32_t height, int32_t tile_size);
@@ -138,7 +145,13 @@ size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* 
  *
  * Inputs (device): depth [n] and rect [n,4] from gs_project (depth must be
  * positive wherever rect is non-empty: its bits are the sort key; a splat
- * with depth +inf reaches no tile and its rect is not read).
+ * with depth +inf reaches no tile and its rect is not read).  With a far
+ * plane (cam->far_plane > 0) the finite depths must also lie in
+ * [near_plane, far_plane], as gs_project leaves them: only the radix passes
+ * that range needs run.  Depths outside it whose keys then span more bits
+ * than those passes sort fail the call with GS_ERR_INVALID_ARGUMENT (the
+ * asynchronous variants report the pair count GS_PAIRS_DEPTH_RANGE instead
+ * and emit nothing); others are still ordered correctly.
  * Outputs:
  *   sorted_ids [capacity] int32  (device) splat indices; tile t's list is
  *                               sorted_ids[tile_ranges[2t] .. tile_ranges[2t+1]),

@@ -64,6 +64,7 @@ typedef struct {
   double view[12];    /* row-major [R | t], world -> camera, OpenCV axes */
   double cam_pos[3];  /* camera centre in world space */
   double near_plane;
+  double far_plane;   /* 0: none */
 } or_camera;
 
 typedef struct {
@@ -196,6 +197,7 @@ void or_project(int64_t n, const double* means, const double* log_scales, const 
       t[r] = ((V[4 * r] * mu[0] + V[4 * r + 1] * mu[1]) + V[4 * r + 2] * mu[2]) + V[4 * r + 3];
     depth[i] = t[2];
     if (!(t[2] > cam->near_plane)) continue;
+    if (cam->far_plane > 0.0 && t[2] > cam->far_plane) continue;
 
     /* world covariance Sigma = R S S^T R^T */
     double R[3][3];

@@ -67,7 +67,7 @@ class _Camera(ctypes.Structure):
                 ("fx", ctypes.c_double), ("fy", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double),
                 ("view", ctypes.c_double * 12), ("cam_pos", ctypes.c_double * 3),
-                ("near_plane", ctypes.c_double)]
+                ("near_plane", ctypes.c_double), ("far_plane", ctypes.c_double)]
 
 
 class _Config(ctypes.Structure):
@@ -118,6 +118,7 @@ def _camera(cam: dict) -> _Camera:
     c.view[:] = list(view)
     c.cam_pos[:] = list(np.asarray(cam["cam_pos"], np.float32).astype(np.float64))
     c.near_plane = float(np.float32(cam["near_plane"]))
+    c.far_plane = float(np.float32(cam.get("far_plane", 0.0)))
     return c
 
 

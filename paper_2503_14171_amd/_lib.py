@@ -35,7 +35,7 @@ class GsCamera(ctypes.Structure):
                 ("fx", ctypes.c_float), ("fy", ctypes.c_float),
                 ("cx", ctypes.c_float), ("cy", ctypes.c_float),
                 ("view", ctypes.c_float * 12), ("cam_pos", ctypes.c_float * 3),
-                ("near_plane", ctypes.c_float)]
+                ("near_plane", ctypes.c_float), ("far_plane", ctypes.c_float)]
 
 
 class GsRasterCfg(ctypes.Structure):
@@ -112,6 +112,7 @@ def camera(cam: dict) -> GsCamera:
     c.view[:] = [float(v) for v in torch.as_tensor(cam["view"]).reshape(12).tolist()]
     c.cam_pos[:] = [float(v) for v in torch.as_tensor(cam["cam_pos"]).reshape(3).tolist()]
     c.near_plane = float(cam["near_plane"])
+    c.far_plane = float(cam.get("far_plane", 0.0))
     return c
 
 
@@ -150,6 +151,18 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+GS_PAIRS_DEPTH_RANGE = 1 << 62  # pair count of an asynchronous bin sort whose depths left [near, far]
+
+
+def check_pair_count(k: int) -> int:
+    """A pair count read back from an asynchronous bin sort; raises on the
+    depth-range error code."""
+    if k == GS_PAIRS_DEPTH_RANGE:
+        raise GsError(GS_ERR_INVALID_ARGUMENT, "bin sort: a finite depth lies outside the cameras' "
+                      "[near_plane, far_plane]")
+    return k
 
 
 def _check(status: int, n_pairs: int | None = None):

@@ -101,7 +101,7 @@ class ViewBatch:
         is brought down to it plus 25 % before the next frame (the pair
         passes size their grids by the capacity); a captured graph is
         captured again either way."""
-        k = int(self.n_pairs.item())
+        k = L.check_pair_count(int(self.n_pairs.item()))
         if k <= self.capacity:
             if self.capacity > 2 * k + 4096:
                 self._shrink_to = int(k * 1.25) + 1024  # before the next frame: ids stay readable

@@ -41,6 +41,9 @@ gs_status check_camera(const char* fn, const gs_camera* cam) {
       return fail(GS_ERR_INVALID_ARGUMENT, "%s: cam_pos not finite", fn);
   if (!(cam->near_plane > 0.f) || !finite(cam->near_plane))
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: near_plane must be finite and > 0", fn);
+  if (!finite(cam->far_plane) || cam->far_plane < 0.f ||
+      (cam->far_plane > 0.f && !(cam->far_plane > cam->near_plane)))
+    return fail(GS_ERR_INVALID_ARGUMENT, "%s: far_plane must be 0 or finite and > near_plane", fn);
   return GS_OK;
 }
 

@@ -26,6 +26,7 @@
 // (wave64 ballot match plus wave-private counters in LDS), reorders them in
 // LDS and writes every digit run contiguously.
 #include <algorithm>
+#include <cstring>
 
 #include "gsup_internal.h"
 
@@ -39,6 +40,10 @@ constexpr int kThreads = 256;
 constexpr int kItems = GSUP_SORT_ITEMS;  // elements per thread of a sort / scan block
 constexpr int kTile = kThreads * kItems;  // elements per sort / scan block
 constexpr int kWaves = kThreads / 64;
+
+// Pair count reported when the depth keys span more than the launched depth
+// passes sort (a depth outside the views' [near_plane, far_plane]).
+constexpr uint64_t kDepthRangeError = uint64_t(GS_PAIRS_DEPTH_RANGE);
 
 // Pair count a device-count pass works on: the emitted total when it fits the
 // capacity (and the int32 index range), else 0 so that every later pass and
@@ -631,19 +636,40 @@ int radix_plan(int bits, int widths[8], int max_bits = kMaxDigitBits) {
   return passes;
 }
 
-// Digit widths of the depth sort: the first pass (over every splat) at the
-// common width, the next two at the tile digit's width, so that depths
-// spanning fewer than 2^26 ulps (8 binades) need three passes; the fourth
-// pass covers the rest of the 32 bits.
-int depth_plan(int widths[8]) {
-  if (kMaxDigitBits == 8 && kMaxTileDigitBits == 9) {
-    widths[0] = 8;
-    widths[1] = 9;
-    widths[2] = 9;
-    widths[3] = 6;
-    return 4;
+// Digit widths of the depth sort and how many passes to launch.  Without a
+// far plane on every view: passes of 8, 9, 9 and 6 bits, the top one
+// skipping itself on the device when the keys span fewer than 2^26 ulps
+// (depths within a factor of 128).  With far planes the key range
+// [near, far] is known on the host and only the passes it needs are
+// launched: 8 + 9 + 9 bits when it spans at most 2^26 ulps above the first
+// pass's base, else 9 + 9 + 9 when 2^27 (a depth ratio of 65536) suffice
+// (on MI355X a 9-bit first pass over every splat costs about 5 us more than
+// an 8-bit one, a skipped top pass about 6 us).  *covered: key bits above
+// the base the launched passes sort, 32 when all four run.
+int depth_plan(const ViewTiles& vt, int widths[8], int* covered) {
+  static_assert(kMaxAnyDigitBits >= 9, "depth plan needs 9-bit digits");
+  *covered = 32;
+  if (vt.bounded && vt.key_hi > vt.key_lo) {
+    const auto span_bits = [&](int first) {
+      const uint32_t range = vt.key_hi - (vt.key_lo & ~((1u << first) - 1u));
+      return 32 - __builtin_clz(range);
+    };
+    if (span_bits(8) <= 26) {
+      widths[0] = 8;
+      widths[1] = widths[2] = 9;
+      *covered = 26;
+      return 3;
+    }
+    if (span_bits(9) <= 27) {
+      widths[0] = widths[1] = widths[2] = 9;
+      *covered = 27;
+      return 3;
+    }
   }
-  return radix_plan(32, widths);
+  widths[0] = 8;
+  widths[1] = widths[2] = 9;
+  widths[3] = 6;
+  return 4;
 }
 
 // ----------------------------------------------------------------------------
@@ -732,6 +758,7 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
                                                      const uint64_t* __restrict__ blk,
                                                      int64_t nblk, ViewTiles vt,
                                                      uint64_t* __restrict__ total, int64_t cap,
+                                                     int covered, uint32_t low_mask,
                                                      uint32_t* __restrict__ tkeys,
                                                      uint32_t* __restrict__ tvals) {
   __shared__ uint32_t s_off[kEmit + 1];
@@ -765,10 +792,15 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
     all += s_a[w];
     pre += s_p[w];
   }
+  const int64_t nk = eff_count(kept, n);
+  // the depth passes launched sort `covered` bits above the base: a key
+  // range wider than that (a depth outside [near_plane, far_plane]) has not
+  // been ordered, so nothing is emitted and K reports the error
+  if (covered < 32 && nk > 0 && (uint64_t)(dinfo[1] - (dinfo[0] & ~low_mask)) >> covered != 0)
+    all = kDepthRangeError;
   if (blockIdx.x == 0 && t == 0) *total = all;
   if (all > (uint64_t)cap || all >= (uint64_t(1) << 31)) return;  // uniform over the block
   const uint64_t base = pre + sub[blockIdx.x];
-  const int64_t nk = eff_count(kept, n);
   const bool second = dinfo[2] != 0u;
   const uint32_t* __restrict__ order = second ? order1 : order0;
   const uint32_t* __restrict__ prect = second ? prect1 : prect0;
@@ -856,6 +888,17 @@ ViewTiles make_view_tiles(int32_t nv, const gs_camera* cams, int32_t tile_size, 
     off += (uint32_t)vt.tiles_x[v] * (uint32_t)vt.tiles_y[v];
   }
   vt.tile_off[nv] = off;
+  vt.bounded = true;
+  vt.key_lo = 0xFFFFFFFFu;
+  vt.key_hi = 0u;
+  for (int v = 0; v < nv; ++v) {
+    uint32_t lo, hi;
+    std::memcpy(&lo, &cams[v].near_plane, 4);
+    std::memcpy(&hi, &cams[v].far_plane, 4);
+    vt.key_lo = std::min(vt.key_lo, lo);
+    vt.key_hi = std::max(vt.key_hi, hi);
+    vt.bounded = vt.bounded && cams[v].far_plane > 0.f;
+  }
   return vt;
 }
 
@@ -940,7 +983,9 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   uint64_t* kept = reinterpret_cast<uint64_t*>(ws + p.off_dinfo + 16);
   const uint64_t* kept_count = kept;
   int widths[8];
-  const int passes_depth = depth_plan(widths);
+  int covered = 32;
+  const int passes_depth = depth_plan(vt, widths, &covered);
+  const uint32_t low_mask = (1u << widths[0]) - 1u;
   int cur = 0, shift = 0;
   for (int k = 0; k < passes_depth; ++k) {
     const uint32_t* kin = k == 0 ? reinterpret_cast<const uint32_t*>(depth) : u32(p.off_gkey[cur]);
@@ -949,7 +994,7 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     dk.info = dinfo;
     dk.kept = kept;
     dk.bstat = u32(p.off_bstat);
-    dk.low_mask = (1u << widths[0]) - 1u;
+    dk.low_mask = low_mask;
     dk.first = k == 0;
     dk.out_index = cur ^ 1;
     // the packed rectangles travel in the same ping-pong order as the ids
@@ -987,13 +1032,16 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   uint32_t* kbuf[2] = {u32(p.off_pkey[0]), u32(p.off_pkey[1])};
   emit_kernel<<<(unsigned)nbe, kEmit, 0, stream>>>(n, order0, order1, prect0, prect1, dinfo,
                                                    kept_count, r4, bsum, bblk, nbc, vt, total,
-                                                   p.capacity, kbuf[0], vbuf[0]);
+                                                   p.capacity, covered, low_mask, kbuf[0], vbuf[0]);
   GS_TRY(hipGetLastError(), "emit_kernel");
   int64_t m = p.capacity;  // device-count mode: grids sized by the capacity
   if (!dev) {
     uint64_t K = 0;
     GS_TRY(hipMemcpyAsync(&K, total, sizeof(K), hipMemcpyDeviceToHost, stream), "pair count copy");
     GS_TRY(hipStreamSynchronize(stream), "pair count sync");
+    if (K == kDepthRangeError)
+      return fail(GS_ERR_INVALID_ARGUMENT,
+                  "gs_bin_sort: a finite depth lies outside the cameras' [near_plane, far_plane]");
     *n_pairs = (int64_t)K;
     if (K >= (uint64_t(1) << 31))
       return fail(GS_ERR_CAPACITY, "gs_bin_sort: %llu pairs exceed the 2^31 index limit",

@@ -52,6 +52,11 @@ struct ViewTiles {
   int64_t n = 0;  // splats per view
   int32_t tiles_x[GS_MAX_VIEWS], tiles_y[GS_MAX_VIEWS];
   uint32_t tile_off[GS_MAX_VIEWS + 1];
+  // FP32 bits of the smallest near plane and the largest far plane of the
+  // views; bounded: every view has a far plane, so every finite depth key
+  // lies in [key_lo, key_hi]
+  uint32_t key_lo = 0, key_hi = 0;
+  bool bounded = false;
 };
 ViewTiles make_view_tiles(int32_t nv, const gs_camera* cams, int32_t tile_size, int64_t n);
 

@@ -33,7 +33,7 @@ struct ProjView {
   double fx, fy, cx, cy;
   double V[12];
   double cam[3];
-  double near_plane;
+  double near_plane, far_plane;  // far_plane 0: none
   double limx, limy;
 };
 
@@ -117,7 +117,8 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
   const double t2 = ((V[8] * mu0 + V[9] * mu1) + V[10] * mu2) + V[11];
   const double qn2 = (double)q4.x * q4.x + (double)q4.y * q4.y + (double)q4.z * q4.z +
                      (double)q4.w * q4.w;
-  ok = ok && (t2 > cv.near_plane) && (qn2 > 0.0) && ((double)sig >= p.alpha_min);
+  ok = ok && (t2 > cv.near_plane) && (cv.far_plane <= 0.0 || t2 <= cv.far_plane) && (qn2 > 0.0) &&
+       ((double)sig >= p.alpha_min);
 
   float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0;
   double2 m2 = make_double2(0.0, 0.0);
@@ -503,6 +504,7 @@ ProjParams make_proj_params(int64_t n, int32_t nv, const gs_camera* cams,
     for (int k = 0; k < 12; ++k) c.V[k] = cam.view[k];
     for (int k = 0; k < 3; ++k) c.cam[k] = cam.cam_pos[k];
     c.near_plane = cam.near_plane;
+    c.far_plane = cam.far_plane;
     c.limx = kFrustumClamp * (0.5 * cam.width) / (double)cam.fx;
     c.limy = kFrustumClamp * (0.5 * cam.height) / (double)cam.fy;
   }

@@ -109,7 +109,7 @@ class Renderer:
         """After gs_bin_sort_async (waits for the stream): True if the pairs fitted;
         otherwise grows the buffers for the next frame and returns False."""
         b = b or self._view_bufs(cam, cfg)
-        k = int(b["n_pairs_dev"].item())
+        k = L.check_pair_count(int(b["n_pairs_dev"].item()))
         b["n_pairs"] = k
         if k <= b["capacity"]:
             if b["capacity"] > 2 * k + 4096:

@@ -120,10 +120,15 @@ def workload_scene(name: str, n: int | None = None, seed: int | None = None) -> 
 
 
 def make_camera(width: int, height: int, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0, 0.0),
-                down=(0.0, 1.0, 0.0), fov_x_deg: float = 60.0, near_plane: float = 0.2) -> dict:
+                down=(0.0, 1.0, 0.0), fov_x_deg: float = 60.0, near_plane: float = 0.2,
+                far_plane: float = 100.0) -> dict:
     """Pinhole camera with OpenCV axes (+x right, +y down, +z forward), looking
     from ``eye`` at ``target``; horizontal field of view ``fov_x_deg``;
-    principal point at the image centre, pixel centres at integer coordinates."""
+    principal point at the image centre, pixel centres at integer coordinates;
+    Gaussians closer than ``near_plane`` or farther than ``far_plane`` (0: no
+    far plane) are culled.  The default far plane, 100, lies beyond every
+    Gaussian of the workloads seen from their cameras (scene extent 10,
+    cameras at distance 3), so it culls nothing there."""
     eye = np.asarray(eye, np.float64)
     z = np.asarray(target, np.float64) - eye
     z /= np.linalg.norm(z)
@@ -136,7 +141,8 @@ def make_camera(width: int, height: int, eye=(0.0, 0.0, -3.0), target=(0.0, 0.0,
     f = width / (2.0 * math.tan(math.radians(fov_x_deg) / 2.0))
     return dict(width=int(width), height=int(height), fx=float(np.float32(f)), fy=float(np.float32(f)),
                 cx=float(np.float32((width - 1) / 2.0)), cy=float(np.float32((height - 1) / 2.0)),
-                view=view, cam_pos=eye.astype(np.float32), near_plane=float(np.float32(near_plane)))
+                view=view, cam_pos=eye.astype(np.float32), near_plane=float(np.float32(near_plane)),
+                far_plane=float(np.float32(far_plane)))
 
 
 def scale_camera(cam: dict, width: int, height: int) -> dict:
@@ -151,6 +157,16 @@ def scale_camera(cam: dict, width: int, height: int) -> dict:
                cx=float(np.float32((cam["cx"] + 0.5) * sx - 0.5)),
                cy=float(np.float32((cam["cy"] + 0.5) * sy - 0.5)))
     return out
+
+
+def depth_bound(scene: dict, cam: dict) -> float:
+    """A far plane that culls none of the scene's Gaussians seen from `cam`:
+    the camera's distance from the origin plus the largest distance of a mean
+    from it (a bound on every mean's camera-space depth), rounded up."""
+    m = np.asarray(scene["means"], np.float64)
+    r = np.sqrt((m[np.isfinite(m).all(1)] ** 2).sum(1)).max(initial=0.0)
+    d = float(np.linalg.norm(np.asarray(cam["cam_pos"], np.float64)))
+    return float(math.ceil(1.001 * (d + r) + 1e-3))
 
 
 def orbit_camera(width: int, height: int, azimuth_deg: float, elevation_deg: float,

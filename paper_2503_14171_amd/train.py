@@ -62,7 +62,7 @@ class TrainViews:
             L.gs_project_views(*args, self.cams, self.cfg, self.splats, self.depth, self.rect)
             L.gs_bin_sort_views(self.n, self.cams, self.cfg, self.depth, self.rect, self.capacity, self.ids,
                                 self.ranges, self.n_pairs, self.workspace)
-            k = int(self.n_pairs.item())
+            k = L.check_pair_count(int(self.n_pairs.item()))
             if k <= self.capacity:
                 # the pair passes size their grids by the capacity: keep it
                 # near the count from the next step on

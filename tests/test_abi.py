@@ -46,9 +46,9 @@ def test_struct_layouts_match_binding(L, tmp_path):
 #include <stddef.h>
 #include "gsup.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gs_camera), offsetof(gs_camera, view),
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gs_camera), offsetof(gs_camera, view),
          offsetof(gs_camera, near_plane), sizeof(gs_raster_cfg), offsetof(gs_raster_cfg, bg),
-         sizeof(gs_splat));
+         sizeof(gs_splat), offsetof(gs_camera, far_plane));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(gs_splat, mean), offsetof(gs_splat, conic),
          offsetof(gs_splat, opacity), offsetof(gs_splat, rgb), offsetof(gs_splat, support));
   return 0;
@@ -60,7 +60,8 @@ int main(void) {
     a = list(map(int, a.split()))
     b = list(map(int, b.split()))
     assert a == [ctypes.sizeof(L.GsCamera), L.GsCamera.view.offset, L.GsCamera.near_plane.offset,
-                 ctypes.sizeof(L.GsRasterCfg), L.GsRasterCfg.bg.offset, 4 * L.SPLAT_FLOATS]
+                 ctypes.sizeof(L.GsRasterCfg), L.GsRasterCfg.bg.offset, 4 * L.SPLAT_FLOATS,
+                 L.GsCamera.far_plane.offset]
     assert b == [0, 16, 28, 32, 44]
 
 
@@ -109,6 +110,10 @@ def test_validation_rejects_bad_calls(L):
     assert lib.gs_last_error_message().decode() == ""
     bad_cam = L.camera(dict(scenes.make_camera(64, 48), near_plane=0.0))
     assert lib.gs_project(10, F, F, F, F, F, R(bad_cam), R(cfg), F, F, F, None) == L.GS_ERR_INVALID_ARGUMENT
+    for far in (-1.0, 0.1, float("inf")):  # negative, before the near plane, not finite
+        bad_far = L.camera(scenes.make_camera(64, 48, far_plane=far))
+        assert lib.gs_project(10, F, F, F, F, F, R(bad_far), R(cfg), F, F, F, None) == L.GS_ERR_INVALID_ARGUMENT
+        assert "far_plane" in lib.gs_last_error_message().decode()
     zero_cam = L.camera(dict(scenes.make_camera(64, 48), width=0))
     assert lib.gs_raster_grad(F, F, F, R(zero_cam), R(cfg), 1, F, None, None) == L.GS_ERR_INVALID_ARGUMENT
     assert lib.gs_raster_grad(F, None, F, R(cam), R(cfg), 1, F, None, None) == L.GS_ERR_INVALID_ARGUMENT

@@ -37,7 +37,7 @@ def _dev(a, dtype=None):
 # ---------------------------------------------------------------------------
 # gs_project
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["tiny", "tiny_deg3_orbit", "clusters_subset"])
+@pytest.mark.parametrize("case", ["tiny", "tiny_deg3_orbit", "clusters_subset", "far_plane"])
 def test_project_matches_oracle(gs, oracle, case):
     import torch
     from paper_2503_14171_amd import scenes
@@ -48,6 +48,9 @@ def test_project_matches_oracle(gs, oracle, case):
         sc = scenes.make_scene("uniform", 20000, 21, 3)
         sc["means"] *= np.float32(2.2)  # near-plane culls and J clamps
         cam = scenes.orbit_camera(200, 120, 40.0, -15.0)
+    elif case == "far_plane":  # a far plane through the scene culls its far half
+        sc = scenes.make_scene("uniform", 20000, 27, 1)
+        cam = scenes.make_camera(320, 240, far_plane=3.0)
     else:
         sc = scenes.make_scene("clusters", 100000, 22, 3)
         cam = scenes.make_camera(960, 540)
@@ -191,7 +194,13 @@ def test_bin_sort_depth_key_ranges(gs, oracle, kind, tile):
     from paper_2503_14171_amd import scenes
     rng = np.random.default_rng(_DEPTH_KINDS.index(kind) + 40)
     n = 70000
-    cam = scenes.make_camera(512, 384)
+    d32 = _depth_set(kind, rng, n)
+    fin = d32[np.isfinite(d32)]
+    # depths inside the default camera's [0.2, 100]: the far plane bounds the
+    # keys and only the passes that range needs run; otherwise no far plane
+    # (every pass may run)
+    inside = fin.size == 0 or (fin.min() >= np.float32(0.2) and fin.max() <= np.float32(100.0))
+    cam = scenes.make_camera(512, 384, far_plane=100.0 if inside else 0.0)
     cfg = scenes.render_config(0, tile_size=tile)
     tx, ty = _tiles_xy(cam, tile)
     x0 = rng.integers(0, tx, n)
@@ -199,13 +208,60 @@ def test_bin_sort_depth_key_ranges(gs, oracle, kind, tile):
     w = rng.integers(1, 3, n)
     h = rng.integers(1, 3, n)
     rect = np.stack([x0, y0, np.minimum(x0 + w, tx), np.minimum(y0 + h, ty)], 1).astype(np.int32)
-    d32 = _depth_set(kind, rng, n)
     rect[np.isinf(d32)] = 0
-    print(f"bin_sort depth keys kind={kind} tile={tile}", flush=True)
+    print(f"bin_sort depth keys kind={kind} tile={tile} far={cam['far_plane']}", flush=True)
     ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
     ref_ids, ref_ranges = oracle.tile_lists(d32, rect, tx, ty)
     np.testing.assert_array_equal(ranges, ref_ranges)
     np.testing.assert_array_equal(ids, ref_ids)
+
+
+def test_bin_sort_depth_outside_near_far_is_refused(gs, oracle):
+    """With a far plane only the depth passes [near, far] needs run (near 0.2,
+    far 50: 8 + 9 + 9 bits, sorting 26 key bits above the smallest depth): a
+    depth so far beyond it that the keys span more bits makes the synchronous
+    sort fail and the asynchronous one report GS_PAIRS_DEPTH_RANGE with empty
+    lists; a depth beyond it whose keys still fit is ordered correctly; inside
+    it, the lists equal a lexicographic sort."""
+    import torch
+    from paper_2503_14171_amd import scenes
+    rng = np.random.default_rng(93)
+    n = 30000
+    cam = scenes.make_camera(256, 192, far_plane=50.0)
+    cfg = scenes.render_config(0, tile_size=16)
+    tx, ty = _tiles_xy(cam, 16)
+    x0 = rng.integers(0, tx, n)
+    y0 = rng.integers(0, ty, n)
+    rect = np.stack([x0, y0, np.minimum(x0 + 2, tx), np.minimum(y0 + 1, ty)], 1).astype(np.int32)
+    d32 = rng.uniform(0.25, 50.0, n).astype(np.float32)
+    d32[0] = np.float32(50.0)  # on the far plane: inside
+    print("bin_sort near/far bounded depths", flush=True)
+    ids, ranges = _run_bin_sort(gs, d32, rect, cam, cfg)
+    ref_ids, ref_ranges = oracle.tile_lists(d32, rect, tx, ty)
+    np.testing.assert_array_equal(ranges, ref_ranges)
+    np.testing.assert_array_equal(ids, ref_ids)
+    fits = d32.copy()
+    fits[n // 3] = np.float32(60.0)  # beyond the far plane, key still within 2^26 ulps of the min
+    ids, ranges = _run_bin_sort(gs, fits, rect, cam, cfg)
+    ref_ids, ref_ranges = oracle.tile_lists(fits, rect, tx, ty)
+    np.testing.assert_array_equal(ranges, ref_ranges)
+    np.testing.assert_array_equal(ids, ref_ids)
+    bad = d32.copy()
+    bad[n // 2] = np.float32(5000.0)  # keys now span more than 2^26 ulps
+    with pytest.raises(gs.GsError) as ei:
+        _run_bin_sort(gs, bad, rect, cam, cfg)
+    assert ei.value.status == gs.GS_ERR_INVALID_ARGUMENT and "far_plane" in str(ei.value)
+    K = int(ref_ids.shape[0])
+    ws = torch.empty(gs.gs_bin_sort_workspace_size(n, K, cam, cfg), dtype=torch.uint8, device="cuda")
+    ids_d = torch.full((K,), -7, dtype=torch.int32, device="cuda")
+    rg_d = torch.full((tx * ty, 2), -7, dtype=torch.int32, device="cuda")
+    kdev = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gs.gs_bin_sort_async(n, _dev(bad), _dev(rect), cam, cfg, K, ids_d, rg_d, kdev, ws)
+    torch.cuda.synchronize()
+    assert int(kdev.item()) == gs.GS_PAIRS_DEPTH_RANGE
+    assert torch.all(rg_d == 0) and torch.all(ids_d == -7)
+    with pytest.raises(gs.GsError):
+        gs.check_pair_count(int(kdev.item()))
 
 
 def test_bin_sort_wide_and_far_rectangles(gs, oracle):

@@ -269,6 +269,22 @@ def test_projection_culls(oracle):
     np.testing.assert_array_equal(pr["valid"], [False, False, False, False, True, True])
 
 
+def test_projection_far_plane(oracle):
+    """The far plane culls exactly the Gaussians with camera z > far_plane
+    (the camera at (0, 0, -3) looks along +z, so z = mean_z + 3); 0 means no
+    far plane."""
+    sc = scenes.make_scene("uniform", 5, 17, 0)
+    sc["means"][:] = [(0.0, 0.0, 1.5), (0.1, 0.0, 2.0), (0.0, 0.1, 2.0000005), (0.0, 0.0, 40.0),
+                      (0.0, 0.0, -1.0)]
+    z = sc["means"][:, 2].astype(np.float64) + 3.0
+    cfg = scenes.render_config(0)
+    for far in (5.0, 43.5):
+        pr = oracle.project(sc, scenes.make_camera(32, 32, far_plane=far), cfg)
+        np.testing.assert_array_equal(pr["valid"], z <= far)
+    pr = oracle.project(sc, scenes.make_camera(32, 32, far_plane=0.0), cfg)
+    assert pr["valid"].all()
+
+
 # ---------------------------------------------------------------------------
 # P11: pixel mapping between resolutions
 # ---------------------------------------------------------------------------
