@@ -453,13 +453,30 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   const int64_t seg = base + wave * kSeg;
   for (int k = t; k < kWaves * R; k += kThreads) (&s_wh[0][0])[k] = 0;
 
-  uint32_t key[kRounds], val[kRounds], rank[kRounds];
+  uint32_t key[kRounds], val[kRounds], rank[kRounds], pay[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t e = seg + r * 64 + lane;
     const bool valid = e < m;
     key[r] = valid ? keys_in[e] : 0u;
     val[r] = valid ? (vals_in ? vals_in[e] : (uint32_t)e) : 0u;
+  }
+  // the payload is loaded with the keys and values, so its latency overlaps
+  // the ranking (the first pass builds it from the projection's rectangles)
+  if (pl.to) {
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t e = seg + r * 64 + lane;
+      pay[r] = 0u;
+      if (e < m && key_kept(dk, key[r])) {
+        if (pl.from) {
+          pay[r] = pl.from[e];
+        } else {
+          const int v = view_of(pl.vt, val[r]);
+          pay[r] = pack_rect(clip_rect(pl.rect[e], pl.vt.tiles_x[v], pl.vt.tiles_y[v]));
+        }
+      }
+    }
   }
   // global digit starts (exclusive scan of the totals) + this block's prefix
   {
@@ -559,16 +576,8 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       if (kept[r]) {
-        const int64_t e = seg + r * 64 + lane;
-        uint32_t py;
-        if (pl.from) {
-          py = pl.from[e];
-        } else {
-          const int v = view_of(pl.vt, val[r]);
-          py = pack_rect(clip_rect(pl.rect[e], pl.vt.tiles_x[v], pl.vt.tiles_y[v]));
-        }
         const uint32_t d = ((key[r] - kbase) >> shift) & (R - 1);
-        s_vals[s_wh[wave][d] + rank[r]] = py;
+        s_vals[s_wh[wave][d] + rank[r]] = pay[r];
       }
     }
     __syncthreads();
@@ -1003,7 +1012,9 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
     pl.rect = r4;
     pl.vt = vt;
     pl.to = u32(p.off_prect[cur ^ 1]);
-    GS_TRY(radix_pass(kin, vin, u32(p.off_gkey[cur ^ 1]), u32(p.off_gval[cur ^ 1]), n,
+    // the keys of the last pass are not read again when no pass can follow it
+    uint32_t* kout = (k + 1 == passes_depth && covered < 32) ? nullptr : u32(p.off_gkey[cur ^ 1]);
+    GS_TRY(radix_pass(kin, vin, kout, u32(p.off_gval[cur ^ 1]), n,
                       k == 0 ? nullptr : kept_count, shift, widths[k], hist, totals, dk, pl,
                       RangesOut{}, stream),
            "depth radix pass");
