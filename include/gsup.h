@@ -311,7 +311,7 @@ gs_status gs_raster_fragment_counts(const gs_splat* splats, const int32_t* sorte
 /* gs_upscale_hermite_views -- one launch for all views.  lo_sizes and
  * hi_sizes are HOST arrays [n_views][2] of (width, height); in holds the
  * views' [h_v, w_v, 12] buffers back to back, out their [H_v, W_v, 3] images.
- * band_rows: output rows per workgroup, 4, 8, 16 or 32 (0 = 8); it changes
+ * band_rows: output rows per workgroup, 4, 8, 16 or 32 (0 = 16); it changes
  * only the speed. */
 gs_status gs_upscale_hermite_views(const float* in, int32_t n_views, const int32_t* lo_sizes,
                                    float* out, const int32_t* hi_sizes, int32_t band_rows,

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void upscale_kernel(UpParams p,
 
 hipError_t launch_upscale(const float* in, int32_t nv, const int32_t* lo_sizes, float* out,
                           const int32_t* hi_sizes, int32_t band_rows, hipStream_t stream) {
-  if (band_rows <= 0) band_rows = 8;
+  if (band_rows <= 0) band_rows = 16;  // measured best for one view (960x540 -> 3840x2160: 27 us vs 29 at 8)
   const UpParams p = make_up_params(nv, lo_sizes, hi_sizes, band_rows, nullptr);
   const int64_t blocks = p.blocks;
   const unsigned grid = (unsigned)xcd_grid(blocks);
