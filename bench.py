@@ -180,13 +180,19 @@ def run_gpu(args):
             st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs]).mean(0)
         return ms, st, last[0]
 
-    ms_step, st_ms, last_set = frames(depth, args.steps, args.warmup, True)
+    # the timed frames record no events: an event between two kernels of a
+    # stream holds the next kernel back until the previous one has drained
+    # (about 5 us per event on MI355X); the stage times come from a second
+    # pass of the same frames with events between the stages
+    ms_step = frames(depth, args.steps, args.warmup, False)[0]
+    st_ms = frames(depth, args.steps, args.warmup, True)[1]
     # one frame at a time: the latency of a frame, and the stages with the GPU
     # to themselves
     # (the output sets then hold that pass's frames: last_set is its last one)
     ms_serial, st_serial = ms_step, st_ms
     if depth > 1:
-        ms_serial, st_serial, last_set = frames(1, args.steps, args.warmup, True)
+        ms_serial = frames(1, args.steps, args.warmup, False)[0]
+    st_serial, last_set = (lambda r: (r[1], r[2]))(frames(1, args.steps, args.warmup, True))
     # the upscaler's own launch duration: back-to-back launches over the
     # rotating buffer sets between two events on the launch stream
     ue = _events(torch, 2)
@@ -249,12 +255,17 @@ def run_gpu(args):
         for _ in range(d + max(1, args.warmup)):
             direct_step()
         torch.cuda.synchronize()
-        devs = [_events(torch, 4) for _ in range(steps)]
+        # timed without events (as the upscaled frames), then the stages of
+        # the same frames with events between them
         t0 = time.perf_counter()
+        for k in range(steps):
+            direct_step()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        devs = [_events(torch, 4) for _ in range(steps)]
         for k in range(steps):
             direct_step(devs[k])
         torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / steps
         assert pipe.pairs_fit(cam_hi, cfg_d)
         st = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in devs]).mean(0)
         if tile != cfg["tile_size"]:

@@ -689,7 +689,10 @@ int depth_plan(const ViewTiles& vt, int widths[8], int* covered) {
 #endif
 constexpr int kEmit = GSUP_EMIT_BLOCK;  // splats per count / emit block
 
-constexpr int kCountPer = 16;                // splats per thread of the count kernel
+#ifndef GSUP_COUNT_PER_THREAD
+#define GSUP_COUNT_PER_THREAD 16
+#endif
+constexpr int kCountPer = GSUP_COUNT_PER_THREAD;  // splats per thread of the count kernel
 constexpr int kCount = kEmit * kCountPer;     // splats per count block
 constexpr int kSubs = kCount / kEmit;         // emit blocks per count block
 static_assert(kCount % kEmit == 0 && kCountPer % 4 == 0, "count / emit blocking");
@@ -776,6 +779,9 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
   __shared__ uint32_t s_w[kEmit / 64];
   __shared__ uint64_t s_a[kEmit / 64], s_p[kEmit / 64];
   const int t = threadIdx.x;
+  const int64_t nk = eff_count(kept, n);
+  const int64_t p0 = (int64_t)blockIdx.x * kEmit;
+  if (p0 >= nk && blockIdx.x != 0) return;  // no splats here (block 0 still reports K)
   // K and this block's first pair: sums over the count blocks
   const int64_t cb = (int64_t)blockIdx.x / kSubs;
   uint64_t all = 0, pre = 0;
@@ -801,7 +807,6 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
     all += s_a[w];
     pre += s_p[w];
   }
-  const int64_t nk = eff_count(kept, n);
   // the depth passes launched sort `covered` bits above the base: a key
   // range wider than that (a depth outside [near_plane, far_plane]) has not
   // been ordered, so nothing is emitted and K reports the error
@@ -813,7 +818,6 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
   const bool second = dinfo[2] != 0u;
   const uint32_t* __restrict__ order = second ? order1 : order0;
   const uint32_t* __restrict__ prect = second ? prect1 : prect0;
-  const int64_t p0 = (int64_t)blockIdx.x * kEmit;
   const int64_t left = nk - p0;
   const int nb = left <= 0 ? 0 : (left < kEmit ? (int)left : kEmit);
   uint32_t c = 0;
