@@ -124,7 +124,7 @@ int64_t gs_num_tiles(int32_t width, int32_t height, int32_t tile_size);
  *   splats [n]        gs_splat records (zeroed for splats that reach no tile)
  *   depth [n]         camera-space z rounded to FP32 (the sort key); +inf when the
  *                     splat reaches no tile (culled or off-screen)
- *   rect [n,4] int32  tile rectangle [tx0, ty0, tx1, ty1) that holds every pixel
+ *   rect [n,4] int16  tile rectangle [tx0, ty0, tx1, ty1) that holds every pixel
  *                     with alpha >= alpha_min; all zero when culled or off-screen
  * A Gaussian is culled when an input is not finite, its camera z <= near_plane,
  * its 2D covariance is not positive definite, or sigma < alpha_min.  The SH
@@ -133,7 +133,7 @@ int64_t gs_num_tiles(int32_t width, int32_t height, int32_t tile_size);
  * half field of view.  n == 0 is a no-op. */
 gs_status gs_project(int64_t n, const float* means, const float* log_scales, const float* quats,
                      const float* opacity, const float* sh, const gs_camera* cam,
-                     const gs_raster_cfg* cfg, gs_splat* splats, float* depth, int32_t* rect,
+                     const gs_raster_cfg* cfg, gs_splat* splats, float* depth, int16_t* rect,
                      void* stream);
 
 /* Bytes of device workspace gs_bin_sort needs for n splats and `capacity` pairs. */
@@ -164,7 +164,7 @@ size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* 
  * If K > capacity the call returns GS_ERR_CAPACITY with *n_pairs = K and the
  * outputs undefined; the caller grows the buffers and calls again.
  * Waits on `stream` once (to read K).  K must stay below 2^31. */
-gs_status gs_bin_sort(int64_t n, const float* depth, const int32_t* rect, const gs_camera* cam,
+gs_status gs_bin_sort(int64_t n, const float* depth, const int16_t* rect, const gs_camera* cam,
                       const gs_raster_cfg* cfg, int64_t capacity, int32_t* sorted_ids,
                       int32_t* tile_ranges, int64_t* n_pairs, void* workspace,
                       size_t workspace_bytes, void* stream);
@@ -176,7 +176,7 @@ gs_status gs_bin_sort(int64_t n, const float* depth, const int32_t* rect, const 
  * after the stream has run, grows the buffers and runs the frame again.
  * Never waits on the stream; safe to capture in a HIP graph.  Same inputs,
  * outputs and workspace as gs_bin_sort. */
-gs_status gs_bin_sort_async(int64_t n, const float* depth, const int32_t* rect,
+gs_status gs_bin_sort_async(int64_t n, const float* depth, const int16_t* rect,
                             const gs_camera* cam, const gs_raster_cfg* cfg, int64_t capacity,
                             int32_t* sorted_ids, int32_t* tile_ranges, int64_t* n_pairs_dev,
                             void* workspace, size_t workspace_bytes, void* stream);
@@ -198,7 +198,7 @@ gs_status gs_bin_sort_async(int64_t n, const float* depth, const int32_t* rect,
  * overlap on one GPU (other streams, other host threads) race and give
  * undefined results; calls on one stream are ordered and safe.  Nothing in
  * the scratch needs to start at zero: every pass writes what it later reads. */
-gs_status gs_bin_sort_async_static(int64_t n, const float* depth, const int32_t* rect,
+gs_status gs_bin_sort_async_static(int64_t n, const float* depth, const int16_t* rect,
                                    const gs_camera* cam, const gs_raster_cfg* cfg,
                                    int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
                                    int64_t* n_pairs_dev, void* stream);
@@ -267,7 +267,7 @@ int64_t gs_num_tiles_views(int32_t n_views, const gs_camera* cams, int32_t tile_
 gs_status gs_project_views(int64_t n, const float* means, const float* log_scales,
                            const float* quats, const float* opacity, const float* sh,
                            int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                           gs_splat* splats, float* depth, int32_t* rect, void* stream);
+                           gs_splat* splats, float* depth, int16_t* rect, void* stream);
 
 /* Bytes of device workspace gs_bin_sort_views needs. */
 size_t gs_bin_sort_views_workspace_size(int64_t n, int32_t n_views, const gs_camera* cams,
@@ -279,7 +279,7 @@ size_t gs_bin_sort_views_workspace_size(int64_t n, int32_t n_views, const gs_cam
  * entries are splat records v * n + i, ordered by (FP32 depth, i).  The pair
  * count goes to n_pairs_dev as in gs_bin_sort_async (same overflow rule). */
 gs_status gs_bin_sort_views(int64_t n, int32_t n_views, const gs_camera* cams,
-                            const gs_raster_cfg* cfg, const float* depth, const int32_t* rect,
+                            const gs_raster_cfg* cfg, const float* depth, const int16_t* rect,
                             int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
                             int64_t* n_pairs_dev, void* workspace, size_t workspace_bytes,
                             void* stream);

@@ -181,12 +181,12 @@ def gs_num_tiles(width: int, height: int, tile_size: int) -> int:
 def gs_project(means, log_scales, quats, opacity, sh, cam: dict, cfg: dict, splats, depth, rect,
                stream=None) -> None:
     """Project n Gaussians; outputs splats [n,12] f32 (gs_splat records),
-    depth [n] f32, rect [n,4] i32."""
+    depth [n] f32, rect [n,4] i16."""
     n = means.shape[0]
     f = torch.float32
     _check(lib().gs_project(n, _ptr(means, f), _ptr(log_scales, f), _ptr(quats, f), _ptr(opacity, f),
                             _ptr(sh, f), ctypes.byref(camera(cam)), ctypes.byref(raster_cfg(cfg)),
-                            _ptr(splats, f), _ptr(depth, f), _ptr(rect, torch.int32), _stream(stream)))
+                            _ptr(splats, f), _ptr(depth, f), _ptr(rect, torch.int16), _stream(stream)))
 
 
 def gs_bin_sort_workspace_size(n: int, capacity: int, cam: dict, cfg: dict) -> int:
@@ -198,7 +198,7 @@ def gs_bin_sort(n: int, depth, rect, cam: dict, cfg: dict, capacity: int, sorted
                 workspace, stream=None) -> int:
     """Per-tile lists; returns the pair count K (raises GsError with .n_pairs if K > capacity)."""
     k = ctypes.c_int64(0)
-    st = lib().gs_bin_sort(n, _ptr(depth, torch.float32), _ptr(rect, torch.int32),
+    st = lib().gs_bin_sort(n, _ptr(depth, torch.float32), _ptr(rect, torch.int16),
                            ctypes.byref(camera(cam)), ctypes.byref(raster_cfg(cfg)), capacity,
                            _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
                            ctypes.byref(k), _ptr(workspace, torch.uint8), workspace.numel(),
@@ -236,7 +236,7 @@ def gs_fd_slopes(img, out, stream=None) -> None:
 def gs_bin_sort_async(n: int, depth, rect, cam: dict, cfg: dict, capacity: int, sorted_ids, tile_ranges,
                       n_pairs_dev, workspace, stream=None) -> None:
     """gs_bin_sort without the wait; the pair count lands in n_pairs_dev (int64 [1])."""
-    _check(lib().gs_bin_sort_async(n, _ptr(depth, torch.float32), _ptr(rect, torch.int32),
+    _check(lib().gs_bin_sort_async(n, _ptr(depth, torch.float32), _ptr(rect, torch.int16),
                                    ctypes.byref(camera(cam)), ctypes.byref(raster_cfg(cfg)), capacity,
                                    _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
                                    _ptr(n_pairs_dev, torch.int64), _ptr(workspace, torch.uint8),
@@ -246,7 +246,7 @@ def gs_bin_sort_async(n: int, depth, rect, cam: dict, cfg: dict, capacity: int, 
 def gs_bin_sort_async_static(n: int, depth, rect, cam: dict, cfg: dict, capacity: int, sorted_ids,
                              tile_ranges, n_pairs_dev, stream=None) -> None:
     """gs_bin_sort_async in the library's static scratch (no workspace, no allocation)."""
-    _check(lib().gs_bin_sort_async_static(n, _ptr(depth, torch.float32), _ptr(rect, torch.int32),
+    _check(lib().gs_bin_sort_async_static(n, _ptr(depth, torch.float32), _ptr(rect, torch.int16),
                                           ctypes.byref(camera(cam)), ctypes.byref(raster_cfg(cfg)), capacity,
                                           _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
                                           _ptr(n_pairs_dev, torch.int64), _stream(stream)))
@@ -264,7 +264,7 @@ def gs_project_views(means, log_scales, quats, opacity, sh, cams, cfg: dict, spl
     f = torch.float32
     _check(lib().gs_project_views(n, _ptr(means, f), _ptr(log_scales, f), _ptr(quats, f), _ptr(opacity, f),
                                   _ptr(sh, f), len(cams), cameras(cams), ctypes.byref(raster_cfg(cfg)),
-                                  _ptr(splats, f), _ptr(depth, f), _ptr(rect, torch.int32), _stream(stream)))
+                                  _ptr(splats, f), _ptr(depth, f), _ptr(rect, torch.int16), _stream(stream)))
 
 
 def gs_bin_sort_views_workspace_size(n: int, cams, cfg: dict, capacity: int) -> int:
@@ -275,7 +275,7 @@ def gs_bin_sort_views_workspace_size(n: int, cams, cfg: dict, capacity: int) -> 
 def gs_bin_sort_views(n: int, cams, cfg: dict, depth, rect, capacity: int, sorted_ids, tile_ranges,
                       n_pairs_dev, workspace, stream=None) -> None:
     _check(lib().gs_bin_sort_views(n, len(cams), cameras(cams), ctypes.byref(raster_cfg(cfg)),
-                                   _ptr(depth, torch.float32), _ptr(rect, torch.int32), capacity,
+                                   _ptr(depth, torch.float32), _ptr(rect, torch.int16), capacity,
                                    _ptr(sorted_ids, torch.int32), _ptr(tile_ranges, torch.int32),
                                    _ptr(n_pairs_dev, torch.int64), _ptr(workspace, torch.uint8),
                                    workspace.numel(), _stream(stream)))

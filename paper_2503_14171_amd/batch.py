@@ -36,7 +36,7 @@ class ViewBatch:
         dev, n, V = renderer.device, max(renderer.n, 1), len(cams)
         self.splats = torch.empty((V * n, L.SPLAT_FLOATS), dtype=torch.float32, device=dev)
         self.depth = torch.empty(V * n, dtype=torch.float32, device=dev)
-        self.rect = torch.empty((V * n, 4), dtype=torch.int32, device=dev)
+        self.rect = torch.empty((V * n, 4), dtype=torch.int16, device=dev)
         self.tiles = L.gs_num_tiles_views(self.cams, self.cfg["tile_size"])
         self.ranges = torch.empty((self.tiles, 2), dtype=torch.int32, device=dev)
         self.lo_px = [w * h for (w, h) in self.lo]

@@ -158,7 +158,7 @@ namespace {
 gs_status project_impl(const char* fn, int64_t n, const float* means, const float* log_scales,
                        const float* quats, const float* opacity, const float* sh, int32_t nv,
                        const gs_camera* cams, const gs_raster_cfg* cfg, gs_splat* splats,
-                       float* depth, int32_t* rect, void* stream) {
+                       float* depth, int16_t* rect, void* stream) {
   GS_CHECK(check_views(fn, nv, cams));
   GS_CHECK(check_cfg(fn, cfg));
   if (n < 0 || n * nv >= (int64_t(1) << 31))
@@ -167,10 +167,10 @@ gs_status project_impl(const char* fn, int64_t n, const float* means, const floa
   if (n == 0) return GS_OK;
   if (!means || !log_scales || !quats || !opacity || !sh || !splats || !depth || !rect)
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL array argument", fn);
-  if (!aligned(quats, 16) || !aligned(sh, 16) || !aligned(splats, 16) || !aligned(rect, 16) ||
+  if (!aligned(quats, 16) || !aligned(sh, 16) || !aligned(splats, 16) || !aligned(rect, 8) ||
       !aligned(means, 4) || !aligned(log_scales, 4) || !aligned(opacity, 4) || !aligned(depth, 4))
     return fail(GS_ERR_INVALID_ARGUMENT,
-                "%s: quats, sh, splats and rect must be 16-byte aligned (others 4-byte)", fn);
+                "%s: quats, sh and splats must be 16-byte aligned, rect 8-byte (others 4-byte)", fn);
   return check_hip(launch_project(n, means, log_scales, quats, opacity, sh, nv, cams, *cfg, splats,
                                   depth, rect, static_cast<hipStream_t>(stream)),
                    "projection launch");
@@ -188,7 +188,7 @@ size_t bin_sort_ws(int64_t n, int32_t nv, const gs_camera* cams, const gs_raster
 }
 
 gs_status bin_sort_impl(const char* fn, int64_t n, int32_t nv, const gs_camera* cams,
-                        const gs_raster_cfg* cfg, const float* depth, const int32_t* rect,
+                        const gs_raster_cfg* cfg, const float* depth, const int16_t* rect,
                         int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
                         int64_t* n_pairs, int64_t* n_pairs_dev, void* workspace,
                         size_t workspace_bytes, void* stream) {
@@ -203,10 +203,10 @@ gs_status bin_sort_impl(const char* fn, int64_t n, int32_t nv, const gs_camera* 
   if ((!n_pairs && !n_pairs_dev) || !tile_ranges || !workspace || (n > 0 && (!depth || !rect)) ||
       (capacity > 0 && !sorted_ids))
     return fail(GS_ERR_INVALID_ARGUMENT, "%s: NULL argument", fn);
-  if ((n > 0 && !aligned(rect, 16)) || !aligned(workspace, 256) || !aligned(tile_ranges, 8) ||
+  if ((n > 0 && !aligned(rect, 8)) || !aligned(workspace, 256) || !aligned(tile_ranges, 8) ||
       (n_pairs_dev && !aligned(n_pairs_dev, 8)))
     return fail(GS_ERR_INVALID_ARGUMENT,
-                "%s: rect must be 16-byte, tile_ranges and n_pairs 8-byte, workspace 256-byte "
+                "%s: rect, tile_ranges and n_pairs must be 8-byte, workspace 256-byte "
                 "aligned", fn);
   const int64_t tiles = total_tiles(nv, cams, cfg->tile_size);
   if (tiles >= (int64_t(1) << 31))
@@ -289,7 +289,7 @@ const char* gs_version(void) { return "gsup 0.1 (gfx950)"; }
 
 gs_status gs_project(int64_t n, const float* means, const float* log_scales, const float* quats,
                      const float* opacity, const float* sh, const gs_camera* cam,
-                     const gs_raster_cfg* cfg, gs_splat* splats, float* depth, int32_t* rect,
+                     const gs_raster_cfg* cfg, gs_splat* splats, float* depth, int16_t* rect,
                      void* stream) {
   g_msg[0] = 0;
   return project_impl("gs_project", n, means, log_scales, quats, opacity, sh, 1, cam, cfg, splats,
@@ -301,7 +301,7 @@ size_t gs_bin_sort_workspace_size(int64_t n, int64_t capacity, const gs_camera* 
   return bin_sort_ws(n, 1, cam, cfg, capacity);
 }
 
-gs_status gs_bin_sort(int64_t n, const float* depth, const int32_t* rect, const gs_camera* cam,
+gs_status gs_bin_sort(int64_t n, const float* depth, const int16_t* rect, const gs_camera* cam,
                       const gs_raster_cfg* cfg, int64_t capacity, int32_t* sorted_ids,
                       int32_t* tile_ranges, int64_t* n_pairs, void* workspace,
                       size_t workspace_bytes, void* stream) {
@@ -311,7 +311,7 @@ gs_status gs_bin_sort(int64_t n, const float* depth, const int32_t* rect, const 
                        tile_ranges, n_pairs, nullptr, workspace, workspace_bytes, stream);
 }
 
-gs_status gs_bin_sort_async(int64_t n, const float* depth, const int32_t* rect,
+gs_status gs_bin_sort_async(int64_t n, const float* depth, const int16_t* rect,
                             const gs_camera* cam, const gs_raster_cfg* cfg, int64_t capacity,
                             int32_t* sorted_ids, int32_t* tile_ranges, int64_t* n_pairs_dev,
                             void* workspace, size_t workspace_bytes, void* stream) {
@@ -321,7 +321,7 @@ gs_status gs_bin_sort_async(int64_t n, const float* depth, const int32_t* rect,
                        tile_ranges, nullptr, n_pairs_dev, workspace, workspace_bytes, stream);
 }
 
-gs_status gs_bin_sort_async_static(int64_t n, const float* depth, const int32_t* rect,
+gs_status gs_bin_sort_async_static(int64_t n, const float* depth, const int16_t* rect,
                                    const gs_camera* cam, const gs_raster_cfg* cfg,
                                    int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
                                    int64_t* n_pairs_dev, void* stream) {
@@ -368,7 +368,7 @@ int64_t gs_num_tiles_views(int32_t n_views, const gs_camera* cams, int32_t tile_
 gs_status gs_project_views(int64_t n, const float* means, const float* log_scales,
                            const float* quats, const float* opacity, const float* sh,
                            int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                           gs_splat* splats, float* depth, int32_t* rect, void* stream) {
+                           gs_splat* splats, float* depth, int16_t* rect, void* stream) {
   g_msg[0] = 0;
   return project_impl("gs_project_views", n, means, log_scales, quats, opacity, sh, n_views, cams,
                       cfg, splats, depth, rect, stream);
@@ -380,7 +380,7 @@ size_t gs_bin_sort_views_workspace_size(int64_t n, int32_t n_views, const gs_cam
 }
 
 gs_status gs_bin_sort_views(int64_t n, int32_t n_views, const gs_camera* cams,
-                            const gs_raster_cfg* cfg, const float* depth, const int32_t* rect,
+                            const gs_raster_cfg* cfg, const float* depth, const int16_t* rect,
                             int64_t capacity, int32_t* sorted_ids, int32_t* tile_ranges,
                             int64_t* n_pairs_dev, void* workspace, size_t workspace_bytes,
                             void* stream) {

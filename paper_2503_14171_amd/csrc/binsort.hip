@@ -128,8 +128,8 @@ __device__ __forceinline__ T block_scan_inplace(T* __restrict__ data, int64_t m,
 // tile rectangles
 // ----------------------------------------------------------------------------
 // Tile rectangle clipped to the tile grid (so no tile id can leave it).
-__device__ __forceinline__ int4 clip_rect(int4 r, int32_t tiles_x, int32_t tiles_y) {
-  return make_int4(max(r.x, 0), max(r.y, 0), min(r.z, tiles_x), min(r.w, tiles_y));
+__device__ __forceinline__ int4 clip_rect(short4 r, int32_t tiles_x, int32_t tiles_y) {
+  return make_int4(max((int)r.x, 0), max((int)r.y, 0), min((int)r.z, tiles_x), min((int)r.w, tiles_y));
 }
 
 __device__ __forceinline__ uint32_t rect_tiles(int4 r) {
@@ -160,7 +160,7 @@ __device__ __forceinline__ int4 unpack_rect(uint32_t c) {
 
 // Clipped rectangle of splat record e from its packed code (or, escaped,
 // from the projection's rectangles).
-__device__ __forceinline__ int4 splat_rect(uint32_t code, uint32_t e, const int4* __restrict__ rect,
+__device__ __forceinline__ int4 splat_rect(uint32_t code, uint32_t e, const short4* __restrict__ rect,
                                            const ViewTiles& vt) {
   if (code != kRectEscape) return unpack_rect(code);
   const int v = view_of(vt, e);
@@ -172,7 +172,7 @@ __device__ __forceinline__ int4 splat_rect(uint32_t code, uint32_t e, const int4
 // the value is the splat record's index) and read from `from` in later ones.
 struct Payload {
   const uint32_t* from = nullptr;
-  const int4* rect = nullptr;
+  const short4* rect = nullptr;
   ViewTiles vt;
   uint32_t* to = nullptr;
 };
@@ -702,7 +702,7 @@ static_assert(kCount % kEmit == 0 && kCountPer % 4 == 0, "count / emit blocking"
 // buffers its last pass wrote).
 __device__ __forceinline__ uint32_t pair_count_at(int64_t p, uint32_t code,
                                                   const uint32_t* __restrict__ order,
-                                                  const int4* __restrict__ rect,
+                                                  const short4* __restrict__ rect,
                                                   const ViewTiles& vt) {
   const uint32_t e = code == kRectEscape ? order[p] : 0u;
   return rect_tiles(splat_rect(code, e, rect, vt));
@@ -718,7 +718,7 @@ __global__ __launch_bounds__(kEmit) void pair_count_kernel(int64_t n,
                                                            const uint32_t* __restrict__ prect1,
                                                            const uint32_t* __restrict__ dinfo,
                                                            const uint64_t* kept,
-                                                           const int4* __restrict__ rect,
+                                                           const short4* __restrict__ rect,
                                                            ViewTiles vt,
                                                            uint64_t* __restrict__ sub,
                                                            uint64_t* __restrict__ blk) {
@@ -765,7 +765,7 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
                                                      const uint32_t* __restrict__ prect1,
                                                      const uint32_t* __restrict__ dinfo,
                                                      const uint64_t* kept,
-                                                     const int4* __restrict__ rect,
+                                                     const short4* __restrict__ rect,
                                                      const uint64_t* __restrict__ sub,
                                                      const uint64_t* __restrict__ blk,
                                                      int64_t nblk, ViewTiles vt,
@@ -956,7 +956,7 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles) {
 }
 
 gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* depth,
-                       const int32_t* rect, int32_t* sorted_ids, int32_t* tile_ranges,
+                       const int16_t* rect, int32_t* sorted_ids, int32_t* tile_ranges,
                        int64_t* n_pairs, int64_t* n_pairs_dev, void* workspace,
                        hipStream_t stream) {
   char* ws = static_cast<char*>(workspace);
@@ -969,7 +969,7 @@ gs_status run_bin_sort(const BinSortPlan& p, const ViewTiles& vt, const float* d
   const bool dev = n_pairs_dev != nullptr;
   uint64_t* total = dev ? reinterpret_cast<uint64_t*>(n_pairs_dev)
                         : reinterpret_cast<uint64_t*>(ws + p.off_total);
-  const int4* r4 = reinterpret_cast<const int4*>(rect);
+  const short4* r4 = reinterpret_cast<const short4*>(rect);
   const int64_t n = p.n;
   hipError_t e;
 #define GS_TRY(expr, what)                         \

@@ -35,7 +35,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t grid) {
 hipError_t launch_project(int64_t n, const float* means, const float* log_scales,
                           const float* quats, const float* opacity, const float* sh, int32_t nv,
                           const gs_camera* cams, const gs_raster_cfg& cfg, gs_splat* splats,
-                          float* depth, int32_t* rect, hipStream_t stream);
+                          float* depth, int16_t* rect, hipStream_t stream);
 
 hipError_t launch_project_backward(int64_t n, const float* means, const float* log_scales,
                                    const float* quats, const float* opacity, const float* sh,
@@ -84,7 +84,7 @@ BinSortPlan make_bin_sort_plan(int64_t n, int64_t capacity, int64_t tiles);
 // fails with GS_ERR_CAPACITY when it does not fit.  Device-count mode: never
 // waits; K goes to *n_pairs_dev and an oversized K leaves every range empty.
 gs_status run_bin_sort(const BinSortPlan& plan, const ViewTiles& vt, const float* depth,
-                       const int32_t* rect, int32_t* sorted_ids, int32_t* tile_ranges,
+                       const int16_t* rect, int32_t* sorted_ids, int32_t* tile_ranges,
                        int64_t* n_pairs, int64_t* n_pairs_dev, void* workspace,
                        hipStream_t stream);
 

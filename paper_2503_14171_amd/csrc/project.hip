@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
                                                       const float* __restrict__ sh,
                                                       gs_splat* __restrict__ splats,
                                                       float* __restrict__ depth_out,
-                                                      int4* __restrict__ rect_out) {
+                                                      short4* __restrict__ rect_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   constexpr int nb = (DEG + 1) * (DEG + 1);
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void project_kernel(ProjParams p, const float*
   sf[1] = w0;
   sf[2] = w1;
   depth_out[o] = dep;
-  rect_out[o] = rect;
+  rect_out[o] = make_short4((short)rect.x, (short)rect.y, (short)rect.z, (short)rect.w);
   }
 }
 
@@ -516,11 +516,11 @@ ProjParams make_proj_params(int64_t n, int32_t nv, const gs_camera* cams,
 hipError_t launch_project(int64_t n, const float* means, const float* log_scales,
                           const float* quats, const float* opacity, const float* sh, int32_t nv,
                           const gs_camera* cams, const gs_raster_cfg& cfg, gs_splat* splats,
-                          float* depth, int32_t* rect, hipStream_t stream) {
+                          float* depth, int16_t* rect, hipStream_t stream) {
   const ProjParams p = make_proj_params(n, nv, cams, cfg);
   const int threads = 256;
   const int64_t blocks = ceil_div(n, threads);
-  int4* r4 = reinterpret_cast<int4*>(rect);
+  short4* r4 = reinterpret_cast<short4*>(rect);
   const dim3 g((unsigned)blocks), b(threads);
 #define GS_PROJ(D)                                                                              \
   if (nv > 1)                                                                                   \

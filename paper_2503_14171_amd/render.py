@@ -43,7 +43,7 @@ class Renderer:
             tiles = L.gs_num_tiles(cam["width"], cam["height"], cfg["tile_size"])
             b = dict(splats=torch.empty((n, L.SPLAT_FLOATS), dtype=torch.float32, device=dev),
                      depth=torch.empty(n, dtype=torch.float32, device=dev),
-                     rect=torch.empty((n, 4), dtype=torch.int32, device=dev),
+                     rect=torch.empty((n, 4), dtype=torch.int16, device=dev),
                      ranges=torch.empty((tiles, 2), dtype=torch.int32, device=dev),
                      capacity=0)
             self._bufs[key] = b

@@ -28,7 +28,7 @@ class TrainViews:
         f, i = torch.float32, torch.int32
         self.splats = torch.empty((V * n1, L.SPLAT_FLOATS), dtype=f, device=device)
         self.depth = torch.empty(V * n1, dtype=f, device=device)
-        self.rect = torch.empty((V * n1, 4), dtype=i, device=device)
+        self.rect = torch.empty((V * n1, 4), dtype=torch.int16, device=device)
         self.tiles = L.gs_num_tiles_views(self.cams, self.cfg["tile_size"])
         self.ranges = torch.empty((self.tiles, 2), dtype=i, device=device)
         self.lo_px = sum(w * h for (w, h) in self.lo)

@@ -71,7 +71,7 @@ def test_guard_bands_forward_chain(gs):
         print(f"guards: forward chain tile={tile}", flush=True)
         splats = Guarded((n, gs.SPLAT_FLOATS), torch.float32)
         depth = Guarded((n,), torch.float32)
-        rect = Guarded((n, 4), torch.int32)
+        rect = Guarded((n, 4), torch.int16)
         gs.gs_project(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"], cam, cfg,
                       splats.t, depth.t, rect.t)
         for g, nm in ((splats, "splats"), (depth, "depth"), (rect, "rect")):
@@ -128,7 +128,7 @@ def test_guard_bands_views_and_backward(gs):
     print("guards: views and backward", flush=True)
     splats = Guarded((V * n, gs.SPLAT_FLOATS), torch.float32)
     depth = Guarded((V * n,), torch.float32)
-    rect = Guarded((V * n, 4), torch.int32)
+    rect = Guarded((V * n, 4), torch.int16)
     gs.gs_project_views(dev["means"], dev["log_scales"], dev["quats"], dev["opacity"], dev["sh"], cams, cfg,
                         splats.t, depth.t, rect.t)
     for g, nm in ((splats, "splats"), (depth, "depth"), (rect, "rect")):

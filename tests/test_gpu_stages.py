@@ -61,13 +61,13 @@ def test_project_matches_oracle(gs, oracle, case):
         n = sc["means"].shape[0]
         splats = torch.zeros((n, 12), dtype=torch.float32, device="cuda")
         depth = torch.zeros(n, dtype=torch.float32, device="cuda")
-        rect = torch.zeros((n, 4), dtype=torch.int32, device="cuda")
+        rect = torch.zeros((n, 4), dtype=torch.int16, device="cuda")
         gs.gs_project(_dev(sc["means"]), _dev(sc["log_scales"]), _dev(sc["quats"]),
                       _dev(sc["opacity"]), _dev(sc["sh"]), cam, cfg, splats, depth, rect)
         torch.cuda.synchronize()
         s = splats.cpu().numpy()
         d = depth.cpu().numpy()
-        r = rect.cpu().numpy()
+        r = rect.cpu().numpy().astype(np.int32)
         ref_rect = oracle.tile_rects(pr, cam["width"], cam["height"], tile)
         np.testing.assert_array_equal(r, ref_rect)
         live = ref_rect[:, 2] > ref_rect[:, 0]
@@ -99,7 +99,7 @@ def _run_bin_sort(gs, depth32, rect, cam, cfg, capacity=None):
     ws = torch.empty(gs.gs_bin_sort_workspace_size(n, cap, cam, cfg), dtype=torch.uint8, device="cuda")
     ids = torch.full((max(cap, 1),), -7, dtype=torch.int32, device="cuda")
     ranges = torch.full((tiles, 2), -7, dtype=torch.int32, device="cuda")
-    k = gs.gs_bin_sort(n, _dev(depth32), _dev(rect), cam, cfg, cap, ids, ranges, ws)
+    k = gs.gs_bin_sort(n, _dev(depth32), _dev(rect.astype(np.int16)), cam, cfg, cap, ids, ranges, ws)
     torch.cuda.synchronize()
     assert k == K
     return ids.cpu().numpy()[:K], ranges.cpu().numpy()
@@ -256,7 +256,7 @@ def test_bin_sort_depth_outside_near_far_is_refused(gs, oracle):
     ids_d = torch.full((K,), -7, dtype=torch.int32, device="cuda")
     rg_d = torch.full((tx * ty, 2), -7, dtype=torch.int32, device="cuda")
     kdev = torch.zeros(1, dtype=torch.int64, device="cuda")
-    gs.gs_bin_sort_async(n, _dev(bad), _dev(rect), cam, cfg, K, ids_d, rg_d, kdev, ws)
+    gs.gs_bin_sort_async(n, _dev(bad), _dev(rect.astype(np.int16)), cam, cfg, K, ids_d, rg_d, kdev, ws)
     torch.cuda.synchronize()
     assert int(kdev.item()) == gs.GS_PAIRS_DEPTH_RANGE
     assert torch.all(rg_d == 0) and torch.all(ids_d == -7)
@@ -318,7 +318,7 @@ def test_bin_sort_capacity_error_and_empty(gs, oracle):
     ws = torch.empty(gs.gs_bin_sort_workspace_size(0, 0, cam, cfg), dtype=torch.uint8, device="cuda")
     rg = torch.full((48, 2), -1, dtype=torch.int32, device="cuda")
     ids0 = torch.empty(1, dtype=torch.int32, device="cuda")
-    k = gs.gs_bin_sort(0, torch.empty(0, device="cuda"), torch.empty((0, 4), dtype=torch.int32, device="cuda"),
+    k = gs.gs_bin_sort(0, torch.empty(0, device="cuda"), torch.empty((0, 4), dtype=torch.int16, device="cuda"),
                        cam, cfg, 0, ids0, rg, ws)
     torch.cuda.synchronize()
     assert k == 0 and torch.all(rg == 0)
@@ -568,7 +568,7 @@ def test_bin_sort_views_matches_per_view_lexsort(gs, oracle, sizes):
     ranges = torch.full((tiles, 2), -7, dtype=torch.int32, device="cuda")
     kdev = torch.zeros(1, dtype=torch.int64, device="cuda")
     print(f"bin_sort views with escaped rectangles {sizes}", flush=True)
-    gs.gs_bin_sort_views(n, cams, cfg, _dev(np.concatenate(depth)), _dev(np.concatenate(rect)), K, ids,
+    gs.gs_bin_sort_views(n, cams, cfg, _dev(np.concatenate(depth)), _dev(np.concatenate(rect).astype(np.int16)), K, ids,
                          ranges, kdev, ws)
     torch.cuda.synchronize()
     assert int(kdev.item()) == K

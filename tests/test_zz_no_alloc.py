@@ -65,7 +65,7 @@ def test_static_scratch_refuses_sizes_beyond_it(gs):
     n, capacity = 1000, 8_000_000  # 12 B per pair of capacity alone exceeds 64 MiB
     assert gs.gs_bin_sort_workspace_size(n, capacity, cam, cfg) > 64 << 20
     depth = torch.ones(n, dtype=torch.float32, device="cuda")
-    rect = torch.zeros((n, 4), dtype=torch.int32, device="cuda")
+    rect = torch.zeros((n, 4), dtype=torch.int16, device="cuda")
     ids = torch.empty(16, dtype=torch.int32, device="cuda")
     ranges = torch.empty((gs.gs_num_tiles(64, 48, 16), 2), dtype=torch.int32, device="cuda")
     k = torch.zeros(1, dtype=torch.int64, device="cuda")
