@@ -199,6 +199,14 @@ constexpr int kRounds = kSeg / 64;     // 64-element rounds per wave
 #define GSUP_MAX_DIGIT_BITS 8
 #endif
 constexpr int kMaxDigitBits = GSUP_MAX_DIGIT_BITS;
+// Downsweep blocks numbered so that every XCD owns one contiguous range of
+// blocks (xcd_block): the digit runs of neighbouring blocks are adjacent in
+// the output and share cache lines, which then meet in one L2 before they
+// are written back instead of leaving several XCDs as partial lines.
+#ifndef GSUP_SORT_XCD
+#define GSUP_SORT_XCD 1
+#endif
+constexpr bool kSortXcd = GSUP_SORT_XCD != 0;
 static_assert(kMaxDigitBits >= 1 && kMaxDigitBits <= 11, "digit width");
 // Widest digit of the pair (tile id) sort: up to 2^kMaxTileDigitBits list
 // tiles sort in a single pass, whose digit counts are then the tile ranges.
@@ -433,12 +441,14 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   constexpr int R = 1 << BITS;
   __shared__ uint32_t s_w[kWaves];
   if (pass_is_identity(dk, shift)) return;
+  const int64_t blk = kSortXcd ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  if (blk >= nblocks) return;
   // a single-pass tile sort: its digit counts are the list lengths (written
   // also when the pair list is empty)
-  if (ro.ranges && blockIdx.x == 0) ranges_from_counts(totals, ro, s_w);
+  if (ro.ranges && blk == 0) ranges_from_counts(totals, ro, s_w);
   if (m_dev) m = eff_count(m_dev, cap);
-  if ((int64_t)blockIdx.x * kTile >= m) return;
-  if (dk.info && blockIdx.x == 0 && threadIdx.x == 0) dk.info[2] = (uint32_t)dk.out_index;
+  if (blk * kTile >= m) return;
+  if (dk.info && blk == 0 && threadIdx.x == 0) dk.info[2] = (uint32_t)dk.out_index;
   constexpr int DPT = R > kThreads ? R / kThreads : 1;  // digits per thread in the digit phases
   __shared__ uint32_t s_keys[kTile];
   __shared__ uint32_t s_vals[kTile];
@@ -449,7 +459,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const uint32_t kbase = depth_base(dk);
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t base = blk * kTile;
   const int64_t seg = base + wave * kSeg;
   for (int k = t; k < kWaves * R; k += kThreads) (&s_wh[0][0])[k] = 0;
 
@@ -492,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
 #pragma unroll
     for (int k = 0; k < DPT; ++k) {
       const int d = t * DPT + k;
-      if (d < R) s_gbase[d] = excl + hist[(int64_t)d * nblocks + blockIdx.x];
+      if (d < R) s_gbase[d] = excl + hist[(int64_t)d * nblocks + blk];
       excl += tv[k];
     }
   }
@@ -603,7 +613,8 @@ hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* k
   hist_scan_kernel<<<1u << BITS, kThreads, 0, stream>>>(hist, nb, totals, dk, shift);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  radix_downsweep_kernel<BITS><<<(unsigned)nb, kThreads, 0, stream>>>(
+  const int64_t grid = kSortXcd ? xcd_grid(nb) : nb;
+  radix_downsweep_kernel<BITS><<<(unsigned)grid, kThreads, 0, stream>>>(
       kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb, dk, pl, ro);
   return hipGetLastError();
 }
