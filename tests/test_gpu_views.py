@@ -122,6 +122,45 @@ def test_views_against_oracle(torch_mod, oracle):
         assert_within(err, masked)
 
 
+@pytest.mark.parametrize("tile", [16, 32])
+def test_batch_workload_against_oracle_sampled(torch_mod, oracle, tile):
+    """The batched stereo workload at full size (1M Gaussians, 16 views: 720x800
+    upscaled x2 and 480x540 upscaled x3, one launch per step) against the oracle
+    at sampled low-res and upscaled pixels of four views, one per camera size
+    and eye, at list tiles 16 and 32."""
+    torch = torch_mod
+    from paper_2503_14171_amd import scenes
+    from paper_2503_14171_amd.batch import ViewBatch
+    from paper_2503_14171_amd.render import Renderer
+    from test_gpu_e2e import _check_upscaled_samples
+    sc = scenes.workload_scene("batch")
+    cams, hi = scenes.stereo_rig()
+    cfg = scenes.render_config(sc["sh_degree"], tile_size=tile)
+    print(f"batch workload tile {tile}: GPU", flush=True)
+    vb = ViewBatch(Renderer(sc), cams, hi, cfg)
+    lows, ups = vb.render()
+    torch.cuda.synchronize()
+    for v in (0, 7, 8, 15):
+        cam = cams[v]
+        w, h = cam["width"], cam["height"]
+        low = lows[v].cpu().numpy()
+        up = ups[v].cpu().numpy()
+        assert np.isfinite(low).all() and np.isfinite(up).all()
+        print(f"batch workload tile {tile}: oracle view {v}", flush=True)
+        proj = oracle.project(sc, cam, cfg)
+        order = oracle.depth_order(proj)
+        rng = np.random.default_rng(100 + v)
+        xs = rng.integers(0, w, 200)
+        ys = rng.integers(0, h, 200)
+        ref = oracle.composite(proj, order, cfg, xs.astype(float), ys.astype(float), variants=True)
+        err, masked = best_variant_error(low[ys, xs], ref)
+        report(f"batch_t{tile}_view{v}_lowres_sampled", summarize(err, masked, ref["out"]))
+        assert_within(err, masked)
+        e_up, amb = _check_upscaled_samples(oracle, proj, order, cfg, (w, h), hi[v], up, 60, 200 + v)
+        report(f"batch_t{tile}_view{v}_upscaled_sampled", summarize(e_up, amb))
+        assert_within(e_up, amb)
+
+
 def test_graph_replays_match_eager(torch_mod):
     torch = torch_mod
     from paper_2503_14171_amd import scenes
