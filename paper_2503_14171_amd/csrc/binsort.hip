@@ -199,14 +199,6 @@ constexpr int kRounds = kSeg / 64;     // 64-element rounds per wave
 #define GSUP_MAX_DIGIT_BITS 8
 #endif
 constexpr int kMaxDigitBits = GSUP_MAX_DIGIT_BITS;
-// Downsweep blocks numbered so that every XCD owns one contiguous range of
-// blocks (xcd_block): the digit runs of neighbouring blocks are adjacent in
-// the output and share cache lines, which then meet in one L2 before they
-// are written back instead of leaving several XCDs as partial lines.
-#ifndef GSUP_SORT_XCD
-#define GSUP_SORT_XCD 1
-#endif
-constexpr bool kSortXcd = GSUP_SORT_XCD != 0;
 static_assert(kMaxDigitBits >= 1 && kMaxDigitBits <= 11, "digit width");
 // Widest digit of the pair (tile id) sort: up to 2^kMaxTileDigitBits list
 // tiles sort in a single pass, whose digit counts are then the tile ranges.
@@ -431,6 +423,12 @@ __global__ __launch_bounds__(kThreads) void hist_scan_kernel(uint32_t* __restric
   if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+// Depth-pass downsweep blocks are numbered so that every XCD owns one
+// contiguous range of blocks (xcd_block): the digit runs of neighbouring
+// blocks are adjacent in the output and share cache lines, which then meet
+// in one L2 before they are written back instead of leaving several XCDs as
+// partial lines.  The pair (tile id) passes keep the plain numbering, which
+// measured faster for them on MI355X.
 template <int BITS>
 __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in /* null: index */,
@@ -441,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   constexpr int R = 1 << BITS;
   __shared__ uint32_t s_w[kWaves];
   if (pass_is_identity(dk, shift)) return;
-  const int64_t blk = kSortXcd ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t blk = dk.info ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   if (blk >= nblocks) return;
   // a single-pass tile sort: its digit counts are the list lengths (written
   // also when the pair list is empty)
@@ -613,7 +611,7 @@ hipError_t radix_pass_bits(const uint32_t* kin, const uint32_t* vin, uint32_t* k
   hist_scan_kernel<<<1u << BITS, kThreads, 0, stream>>>(hist, nb, totals, dk, shift);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t grid = kSortXcd ? xcd_grid(nb) : nb;
+  const int64_t grid = dk.info ? xcd_grid(nb) : nb;  // depth passes: XCD-numbered blocks
   radix_downsweep_kernel<BITS><<<(unsigned)grid, kThreads, 0, stream>>>(
       kin, vin, kout, vout, m, m_dev, m, shift, hist, totals, nb, dk, pl, ro);
   return hipGetLastError();
