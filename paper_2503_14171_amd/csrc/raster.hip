@@ -111,20 +111,21 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
       const float4 c = s[2];  // r, g, b, support
       const float mx = (float)(m.x - ox), my = (float)(m.y - oy);
       s_a[t] = make_float4(mx, my, q.x, q.y);
-      s_b[t] = make_float4(q.z, log2f(q.w), c.w, c.x);
+      s_b[t] = make_float4(q.z, opacity_log2(q.w), c.w, c.x);
       s_c[t] = make_float4(c.y, c.z, 0.f, 0.f);
       if (NW > 1) {
         // quadrants met by the box of {d^T Q d <= support}: half extents
         // sqrt(support Sigma'_xx), Sigma'_xx = c / (a c - b^2)
         const float det = q.x * q.z - q.y * q.y;
         if (det > 0.f) {
-          const float rx = sqrtf(fmaxf(c.w * q.z / det, 0.f)) + kCullMargin;
-          const float ry = sqrtf(fmaxf(c.w * q.x / det, 0.f)) + kCullMargin;
+          const float idet = stage_rcp(det);
+          const float rx = stage_sqrt(fmaxf(c.w * q.z * idet, 0.f)) + kCullMargin;
+          const float ry = stage_sqrt(fmaxf(c.w * q.x * idet, 0.f)) + kCullMargin;
           int qx0, qx1, qy0, qy1;
           quad_span<QX>(mx, rx, qx0, qx1);
           quad_span<QX>(my, ry, qy0, qy1);
           const bool exact = q.x > 0.f && q.z > 0.f;
-          const float ia = exact ? 1.f / q.x : 0.f, ic = exact ? 1.f / q.z : 0.f;
+          const float ia = exact ? stage_rcp(q.x) : 0.f, ic = exact ? stage_rcp(q.z) : 0.f;
           for (int qy = qy0; qy <= qy1; ++qy)
             for (int qx = qx0; qx <= qx1; ++qx)
               if (!exact || quad_reaches(mx, my, q.x, q.y, q.z, ia, ic, c.w, 8.f * qx, 8.f * qy))

@@ -45,6 +45,16 @@ __device__ __forceinline__ void tile_block(int64_t bid, int sub2, int64_t& tile,
 // (covers FP32 rounding of the box and of the per-pixel alpha test).
 constexpr float kCullMargin = 0.25f;
 
+// Staging-time bounds (the box and the quadrant test below) only have to
+// keep every quadrant with a pixel above alpha_min, and the kCullMargin
+// widening moves the quadratic's minimum by far more than an ulp: they use
+// the hardware reciprocal and square root (about 1 ulp) instead of the
+// correctly rounded sequences.  Opacities are normal numbers (>= alpha_min),
+// so the hardware log2 equals log2f for them.
+__device__ __forceinline__ float stage_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float stage_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float opacity_log2(float x) { return __builtin_amdgcn_logf(x); }
+
 // Quadrants [k0, k1] along one axis (quadrant k holds the pixel centres
 // 8k .. 8k+7 of the workgroup) that the box [m - r, m + r] meets; empty when
 // k0 > k1.  Clamped in float before the conversion, since converting a float
