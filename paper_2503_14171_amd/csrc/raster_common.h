@@ -46,10 +46,12 @@ __device__ __forceinline__ void tile_block(int64_t bid, int sub2, int64_t& tile,
 constexpr float kCullMargin = 0.25f;
 
 // Staging-time bounds (the box and the quadrant test below) only have to
-// keep every quadrant with a pixel above alpha_min, and the kCullMargin
-// widening moves the quadratic's minimum by far more than an ulp: they use
-// the hardware reciprocal and square root (about 1 ulp) instead of the
-// correctly rounded sequences.  Opacities are normal numbers (>= alpha_min),
+// keep every quadrant with a pixel above alpha_min: they use the hardware
+// reciprocal and square root (about 1 ulp) instead of the correctly rounded
+// sequences.  The box half-extents' relative error of a few 1e-7 is far
+// inside the kCullMargin widening, and an approximate 1/a or 1/c only moves
+// the minimiser along an edge, which changes the edge minimum to second
+// order.  Opacities are normal numbers (>= alpha_min),
 // so the hardware log2 equals log2f for them.
 __device__ __forceinline__ float stage_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float stage_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }

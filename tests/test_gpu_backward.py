@@ -18,7 +18,7 @@ state.
 import numpy as np
 import pytest
 
-from parity_util import rounded_proj, splat_records
+from parity_util import report, rounded_proj, splat_records
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +69,8 @@ def test_upscale_backward_matches_oracle(torch_mod):
     a = 0
     for (w, h), g in zip(lo, gs):
         ref = oracle.upscale_adjoint(g.astype(np.float64), w, h).reshape(-1, 12)
+        report(f"bwd_upscale_{w}x{h}", {"max_abs_err": float(np.abs(got[a:a + w * h] - ref).max()),
+                                        "ref_max": float(np.abs(ref).max())})
         np.testing.assert_allclose(got[a:a + w * h], ref, atol=2e-5 * max(1.0, np.abs(ref).max()), rtol=1e-5)
         a += w * h
 
@@ -126,6 +128,7 @@ def test_raster_backward_matches_oracle(torch_mod, oracle, tile, bg):
     for f, name in enumerate(oracle.SPLAT_GRAD):
         e = _rel_err(got[:, f], ref[:, f])
         print(f"  {name}: rel err {e:.2e}", flush=True)
+        report(f"bwd_raster_t{tile}_bg{int(any(bg))}_{name}", {"mixed_err": e})
         assert e < REL, name
 
 
@@ -157,6 +160,7 @@ def test_project_backward_matches_oracle(torch_mod, oracle):
     for k in oracle.PARAMS:
         e = _rel_err(out[k].cpu().numpy(), ref[k])
         print(f"  {k}: rel err {e:.2e}", flush=True)
+        report(f"bwd_project_{k}", {"mixed_err": e})
         assert e < REL, k
 
 
@@ -204,6 +208,7 @@ def test_training_chain_matches_oracle_and_finite_differences(torch_mod, oracle)
         got = params[k].grad.cpu().numpy()
         e = _rel_err(got, ref[k])
         print(f"  {k}: rel err vs oracle adjoint {e:.2e}", flush=True)
+        report(f"bwd_chain_{k}", {"mixed_err": e})
         assert e < REL, k
     # direct FP64 finite differences of the oracle's forward on a few entries
     def lin_loss(s):
@@ -228,6 +233,7 @@ def test_training_chain_matches_oracle_and_finite_differences(torch_mod, oracle)
             dn_s[k][idx] -= hstep
             fd = (lin_loss(up_s) - lin_loss(dn_s)) / (2 * hstep)
             print(f"  FD {k}{tuple(int(i) for i in idx)}: gpu {got[idx]:.6e} fd {fd:.6e}", flush=True)
+            report(f"bwd_fd_{k}_{checked % 3}", {"rel_err": float(abs(got[idx] - fd) / max(abs(fd), 1e-12))})
             assert abs(got[idx] - fd) <= REL * max(abs(fd), 1e-12), (k, idx, got[idx], fd)
             checked += 1
     assert checked == 15
@@ -310,6 +316,7 @@ def test_raster_backward_dense_scene_sampled(torch_mod, oracle, opaque):
     for f, name in enumerate(oracle.SPLAT_GRAD):
         e = _rel_err(got[:, f], ref[:, f])
         print(f"  {name}: err {e:.2e} (mixed bound, pass < {REL:.0e})", flush=True)
+        report(f"bwd_dense_{'opaque' if opaque else 'plain'}_{name}", {"mixed_err": e})
         assert e < REL, name
 
 
