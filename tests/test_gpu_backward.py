@@ -233,7 +233,7 @@ def test_training_chain_matches_oracle_and_finite_differences(torch_mod, oracle)
             dn_s[k][idx] -= hstep
             fd = (lin_loss(up_s) - lin_loss(dn_s)) / (2 * hstep)
             print(f"  FD {k}{tuple(int(i) for i in idx)}: gpu {got[idx]:.6e} fd {fd:.6e}", flush=True)
-            report(f"bwd_fd_{k}_{checked % 3}", {"rel_err": float(abs(got[idx] - fd) / max(abs(fd), 1e-12))})
+            report(f"bwd_fd_{k}_{checked % 3}", {"rel_err": abs(float(got[idx]) - fd) / max(abs(fd), 1e-12)})
             assert abs(got[idx] - fd) <= REL * max(abs(fd), 1e-12), (k, idx, got[idx], fd)
             checked += 1
     assert checked == 15
