@@ -85,12 +85,6 @@ int64_t total_tiles(int32_t nv, const gs_camera* cams, int32_t tile) {
   return t;
 }
 
-int64_t total_pixels(int32_t nv, const gs_camera* cams) {
-  int64_t t = 0;
-  for (int v = 0; v < nv; ++v) t += (int64_t)cams[v].width * cams[v].height;
-  return t;
-}
-
 // Bin/sort scratch of gs_bin_sort_async_static: a device array that every
 // GPU the library runs on holds from the code object's load to the end of
 // the process.  Host code never uses the array's name as an address (on the
