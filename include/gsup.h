@@ -191,7 +191,8 @@ gs_status gs_bin_sort_async(int64_t n, const float* depth, const int16_t* rect,
  * call on that GPU to the end of the process) takes its place.  Same inputs,
  * outputs, overflow rule and results as gs_bin_sort_async.  Sizes whose
  * workspace, gs_bin_sort_workspace_size(n, capacity, ..), exceeds the scratch
- * (e.g. more than 500k splats with 4M pairs) are rejected with
+ * (about 24 bytes per splat and 12 per pair of capacity: 500k splats with a
+ * capacity of 4M pairs fit, 1M splats with 4M do not) are rejected with
  * GS_ERR_INVALID_ARGUMENT before anything is enqueued.  The call allocates
  * nothing: the scratch's device address is looked up once per device, on the
  * first call there.  Every call on one GPU shares that scratch, so calls that
