@@ -350,7 +350,9 @@ def run_gpu(args):
     # same frames in flight; last, since it reuses the frame's buffers
     orbit = None
     if not args.no_orbit:
-        n_o = max(3, min(args.steps, 10))
+        # 30 frames per camera: with frames in flight, filling and draining
+        # the pipeline weighs more on the shorter upscaled frames
+        n_o = max(3, min(args.steps, 30))
         per = []
         for k in range(8):
             cam_o = scenes.orbit_camera(w, h, 45.0 * k, 15.0)
