@@ -265,20 +265,21 @@ def test_e2e_fractional_and_per_axis_scales(torch_mod, oracle, name, scale):
     _full_size_case(torch_mod, oracle, name, scale, 120, 150)
 
 
-def test_direct_4k_render_tile64_sampled(torch_mod, oracle):
+@pytest.mark.parametrize("tile", [64, 32, 16])
+def test_direct_4k_render_sampled(torch_mod, oracle, tile):
     """The speed-up's denominator and the PSNR reference: the direct 3840x2160
     render of the 3M-Gaussian scene (plain compositing at the high-res
-    camera, 64x64 list tiles, the benchmark's best direct setting) against the
-    oracle's composite at the same camera on 900 sampled pixels (300 in the
-    four densest list tiles, 300 on 64x64 / 16x16 tile borders, 300
-    uniform)."""
+    camera) at each list tile the benchmark times (64x64 is its best direct
+    setting) against the oracle's composite at the same camera on 900 sampled
+    pixels (300 in the four densest list tiles, 300 on list-tile / 16x16
+    borders, 300 uniform)."""
     torch = torch_mod
     from paper_2503_14171_amd import scenes
     from paper_2503_14171_amd.render import Renderer
     sc = scenes.workload_scene("scene")
     cam_hi = scenes.scale_camera(scenes.workload_camera("scene"), 3840, 2160)
-    cfg = scenes.render_config(sc["sh_degree"], tile_size=64)
-    print("direct 4K tile 64: GPU", flush=True)
+    cfg = scenes.render_config(sc["sh_degree"], tile_size=tile)
+    print(f"direct 4K tile {tile}: GPU", flush=True)
     out = Renderer(sc).render(cam_hi, cfg, want_grads=False)
     torch.cuda.synchronize()
     out = out.cpu().numpy()
@@ -286,13 +287,13 @@ def test_direct_4k_render_tile64_sampled(torch_mod, oracle):
     print("direct 4K: oracle projection", flush=True)
     proj = oracle.project(sc, cam_hi, cfg)
     order = oracle.depth_order(proj)
-    dens = _tile_density(oracle, proj, 3840, 2160, 64)
-    rng = np.random.default_rng(11)
-    xs, ys = _stratified_pixels(rng, 3840, 2160, 64, dens, 300, 300, 300)
+    dens = _tile_density(oracle, proj, 3840, 2160, tile)
+    rng = np.random.default_rng(11 + tile)
+    xs, ys = _stratified_pixels(rng, 3840, 2160, tile, dens, 300, 300, 300)
     print(f"direct 4K: oracle composite at {xs.size} pixels", flush=True)
     ref = _oracle_nodes(oracle, proj, order, cfg, xs, ys)
     err, masked = best_variant_error(out[ys, xs], ref)
-    report("direct_scene_3840x2160_t64_sampled", summarize(err, masked, ref["out"][:, :3]))
+    report(f"direct_scene_3840x2160_t{tile}_sampled", summarize(err, masked, ref["out"][:, :3]))
     assert_within(err, masked)
 
 
