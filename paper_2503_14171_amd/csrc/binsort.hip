@@ -385,15 +385,14 @@ __global__ __launch_bounds__(kThreads) void radix_upsweep_kernel(const uint32_t*
     key[r] = e < m ? keys[e] : 0u;
   }
   __syncthreads();
-  const uint64_t lt = lanes_below(lane);
   const uint32_t base = depth_base(dk);
   uint32_t lo = 0xFFFFFFFFu, hi = 0u, kept = 0u;
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const bool valid = seg + r * 64 + lane < m && key_kept(dk, key[r]);
     const uint32_t d = ((key[r] - base) >> shift) & (R - 1);
-    const uint64_t same = match_digit<BITS>(d, valid);
-    if (valid && (same & lt) == 0) s_h[wave][d] += (uint32_t)__popcll(same);
+    // counts only (no ranks here): one LDS atomic add per key
+    if (valid) atomicAdd(&s_h[wave][d], 1u);
     if (valid) {
       lo = min(lo, key[r]);
       hi = max(hi, key[r]);
