@@ -447,7 +447,8 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   if (blk * kTile >= m) return;
   if (dk.info && blk == 0 && threadIdx.x == 0) dk.info[2] = (uint32_t)dk.out_index;
   constexpr int DPT = R > kThreads ? R / kThreads : 1;  // digits per thread in the digit phases
-  __shared__ uint32_t s_keys[kTile];
+  // s_keys also holds, while ranking, each wave's R 64-bit lane masks
+  __shared__ __align__(16) uint32_t s_keys[kTile];
   __shared__ uint32_t s_vals[kTile];
   __shared__ uint32_t s_wh[kWaves][R];  // per-wave digit counts, then per-wave bases
   __shared__ uint32_t s_gbase[R];
@@ -505,7 +506,18 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   }
   __syncthreads();
 
-  // 1. rank within the wave's segment (dropped keys take no rank)
+  // 1. rank within the wave's segment (dropped keys take no rank).  With
+  // 9-bit digits the lanes holding digit d are found by each OR-ing its bit
+  // into the wave's mask word for d in LDS, reading the word back and
+  // clearing it: a wave's LDS operations take effect in issue order, so
+  // every lane reads the mask of all lanes with its digit (three LDS
+  // operations instead of nine ballots and their mask arithmetic).  The
+  // words live in s_keys, which is not used until step 3.  Narrower digits
+  // use the ballot match (fewer ballots, and more lanes share a word).
+  constexpr bool kMaskWords = BITS >= 9 && (int64_t)kWaves * R * 8 <= (int64_t)kTile * 4;
+  uint64_t* const words = reinterpret_cast<uint64_t*>(s_keys) + (kMaskWords ? wave * R : 0);
+  if (kMaskWords)
+    for (int k = lane; k < R; k += 64) words[k] = 0ull;
   const uint64_t lt = lanes_below(lane);
   bool kept[kRounds];
 #pragma unroll
@@ -513,7 +525,14 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     const bool valid = seg + r * 64 + lane < m && key_kept(dk, key[r]);
     kept[r] = valid;
     const uint32_t d = ((key[r] - kbase) >> shift) & (R - 1);
-    const uint64_t same = match_digit<BITS>(d, valid);
+    uint64_t same;
+    if constexpr (kMaskWords) {
+      if (valid) atomicOr(&words[d], 1ull << lane);
+      same = valid ? words[d] : 0ull;
+      if (valid) words[d] = 0ull;
+    } else {
+      same = match_digit<BITS>(d, valid);
+    }
     const uint32_t below = (uint32_t)__popcll(same & lt);
     const uint32_t old = s_wh[wave][d];
     if (valid && below == 0) s_wh[wave][d] = old + (uint32_t)__popcll(same);
