@@ -452,7 +452,6 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   __shared__ uint32_t s_vals[kTile];
   __shared__ uint32_t s_wh[kWaves][R];  // per-wave digit counts, then per-wave bases
   __shared__ uint32_t s_gbase[R];
-  __shared__ uint32_t s_lstart[R];
   __shared__ uint32_t s_count;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -561,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     for (int k = 0; k < DPT; ++k) {
       const int d = t * DPT + k;
       if (d < R) {
-        s_lstart[d] = excl;
+        s_gbase[d] -= excl;  // global start minus block-local start: dst = s_gbase[d] + i
         uint32_t run = excl;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
@@ -591,7 +590,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   for (int i = t; i < count; i += kThreads) {
     const uint32_t k = s_keys[i];
     const uint32_t d = ((k - kbase) >> shift) & (R - 1);
-    const uint32_t dst = s_gbase[d] + (uint32_t)i - s_lstart[d];
+    const uint32_t dst = s_gbase[d] + (uint32_t)i;
     if (keys_out) keys_out[dst] = k;  // null: values only (no later pass reads the keys)
     vals_out[dst] = s_vals[i];
   }
@@ -609,7 +608,7 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     __syncthreads();
     for (int i = t; i < count; i += kThreads) {
       const uint32_t d = ((s_keys[i] - kbase) >> shift) & (R - 1);
-      pl.to[s_gbase[d] + (uint32_t)i - s_lstart[d]] = s_vals[i];
+      pl.to[s_gbase[d] + (uint32_t)i] = s_vals[i];
     }
   }
 }
