@@ -401,8 +401,10 @@ def run_batch(args):
     cfg0 = scenes.render_config(sc["sh_degree"])
     rd = Renderer(sc)
     t0 = time.perf_counter()
-    tuned = autotune.tune(rd, cams, hi, cfg0, reps=5)
-    tuned_d = autotune.tune(rd, cams, hi, cfg0, reps=3, direct=True, tiles=(16, 32, 64), batch_divs=(1, 2))
+    # near ties on one stream are settled with the benchmark's frames in flight
+    tuned = autotune.tune(rd, cams, hi, cfg0, reps=5, inflight=args.inflight)
+    tuned_d = autotune.tune(rd, cams, hi, cfg0, reps=3, direct=True, tiles=(16, 32, 64), batch_divs=(1, 2),
+                            inflight=args.inflight)
     tune_s = time.perf_counter() - t0
     cfg = dict(cfg0, tile_size=tuned["tile_size"], batch=tuned["batch"])
     cfg_d = dict(cfg0, tile_size=tuned_d["tile_size"], batch=tuned_d["batch"])
