@@ -20,11 +20,13 @@
 //
 // Radix passes use digits of up to GSUP_MAX_DIGIT_BITS bits (default 8; the
 // key bits are split evenly over the fewest passes; on MI355X 11-bit digits
-// measured slower: their LDS footprint allows one block per CU): an upsweep kernel histograms each
-// 4096-element block, one workgroup per digit scans that digit's counts over
-// the blocks, and a downsweep kernel ranks each block's elements stably
-// (wave64 ballot match plus wave-private counters in LDS), reorders them in
-// LDS and writes every digit run contiguously.
+// measured slower: their LDS footprint allows one block per CU): an upsweep
+// kernel counts each 4096-element block's digits (LDS atomic adds into
+// wave-private counts), one workgroup per digit scans that digit's counts
+// over the blocks, and a downsweep kernel ranks each block's elements stably
+// (each lane finds the lanes of its wave holding its digit, then the lowest
+// of them advances the wave's private counter in LDS), reorders them in LDS
+// and writes every digit run contiguously.
 #include <algorithm>
 #include <cstring>
 
@@ -188,10 +190,12 @@ struct Payload {
 //
 // Every block owns kTile consecutive elements; wave w of the block owns the
 // contiguous quarter [w * kSeg, (w + 1) * kSeg) and walks it 64 elements at a
-// time.  Lanes holding the same digit are found with BITS ballots (wave64
-// match); the lowest such lane updates the wave's private digit counter in
+// time.  In the downsweep, the lanes holding the same digit are found through
+// a 64-bit LDS mask word per digit (9-bit digits) or BITS ballots (narrower
+// ones); the lowest such lane updates the wave's private digit counter in
 // LDS.  No block barrier is needed while ranking, and equal digits keep
-// their input order (wave-major, then round, then lane).
+// their input order (wave-major, then round, then lane).  The upsweep needs
+// only counts: one LDS atomic add per element.
 // ----------------------------------------------------------------------------
 constexpr int kSeg = kTile / kWaves;   // elements per wave
 constexpr int kRounds = kSeg / 64;     // 64-element rounds per wave
