@@ -726,6 +726,7 @@ constexpr int kCountPer = GSUP_COUNT_PER_THREAD;  // splats per thread of the co
 constexpr int kCount = kEmit * kCountPer;     // splats per count block
 constexpr int kSubs = kCount / kEmit;         // emit blocks per count block
 static_assert(kCount % kEmit == 0 && kCountPer % 4 == 0, "count / emit blocking");
+static_assert((kEmit & (kEmit - 1)) == 0, "the owner search halves kEmit");
 
 // Tile count of depth-order position p (the depth sort left only the splats
 // with a finite depth, kept[0] of them, in the order and packed-rectangle
@@ -864,20 +865,22 @@ __global__ __launch_bounds__(kEmit) void emit_kernel(int64_t n, const uint32_t* 
   if (t == 0) s_off[nb] = tot;
   __syncthreads();
   for (uint32_t k = t; k < tot; k += kEmit) {
-    // owner: the last j with s_off[j] <= k (splats without tiles have s_off[j] == s_off[j+1])
-    int lo = 0, hi = nb;  // invariant: s_off[lo] <= k < s_off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_off[mid] <= k) lo = mid;
-      else hi = mid;
-    }
+    // owner: the last j with s_off[j] <= k (splats without tiles have
+    // s_off[j] == s_off[j+1]); a fixed-step search over all kEmit entries:
+    // those from nb on hold tot > k (their threads had no splat)
+    int lo = 0;
+#pragma unroll
+    for (int step = kEmit / 2; step >= 1; step >>= 1)
+      if (s_off[lo + step] <= k) lo += step;
     const int4 r = s_rect[lo];
     const uint32_t gid = s_gid[lo];
     const int v = view_of(vt, gid);
     const uint32_t li = k - s_off[lo];
     const uint32_t w = (uint32_t)(r.z - r.x);
-    // row / column inside the rectangle; the float quotient is exact to +-1
-    int dy = (int)(((float)li + 0.5f) / (float)w);
+    // row / column inside the rectangle: li < w h with h at most 4096 tiles
+    // (32768-pixel images, 8-pixel tiles), so the quotient is below 4097 and
+    // the hardware reciprocal's error is far inside the +-1 correction
+    int dy = (int)(((float)li + 0.5f) * __builtin_amdgcn_rcpf((float)w));
     int dx = (int)li - dy * (int)w;
     if (dx < 0) {
       --dy;
