@@ -523,11 +523,13 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
     for (int k = lane; k < R; k += 64) words[k] = 0ull;
   const uint64_t lt = lanes_below(lane);
   bool kept[kRounds];
+  uint32_t dig[kRounds];  // each element's digit, kept for steps 3 and 5
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const bool valid = seg + r * 64 + lane < m && key_kept(dk, key[r]);
     kept[r] = valid;
     const uint32_t d = ((key[r] - kbase) >> shift) & (R - 1);
+    dig[r] = d;
     uint64_t same;
     if constexpr (kMaskWords) {
       if (valid) atomicOr(&words[d], 1ull << lane);
@@ -577,13 +579,15 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   }
   __syncthreads();
 
-  // 3. reorder the block in LDS by digit
+  // 3. reorder the block in LDS by digit (rank becomes the block position).
+  // A pass that writes no keys stores each element's output index in the
+  // key slot instead, so steps 4 and 5 need no digit lookup.
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     if (kept[r]) {
-      const uint32_t d = ((key[r] - kbase) >> shift) & (R - 1);
-      const uint32_t pos = s_wh[wave][d] + rank[r];
-      s_keys[pos] = key[r];
+      const uint32_t pos = s_wh[wave][dig[r]] + rank[r];
+      rank[r] = pos;
+      s_keys[pos] = keys_out ? key[r] : s_gbase[dig[r]] + pos;
       s_vals[pos] = val[r];
     }
   }
@@ -593,26 +597,27 @@ __global__ __launch_bounds__(kThreads) void radix_downsweep_kernel(
   const int count = (int)s_count;
   for (int i = t; i < count; i += kThreads) {
     const uint32_t k = s_keys[i];
-    const uint32_t d = ((k - kbase) >> shift) & (R - 1);
-    const uint32_t dst = s_gbase[d] + (uint32_t)i;
-    if (keys_out) keys_out[dst] = k;  // null: values only (no later pass reads the keys)
-    vals_out[dst] = s_vals[i];
+    if (keys_out) {
+      const uint32_t dst = s_gbase[((k - kbase) >> shift) & (R - 1)] + (uint32_t)i;
+      keys_out[dst] = k;
+      vals_out[dst] = s_vals[i];
+    } else {  // values only (no later pass reads the keys)
+      vals_out[k] = s_vals[i];
+    }
   }
 
   // 5. the payload, through the value slots of LDS: same positions, same runs
   if (pl.to) {
     __syncthreads();  // step 4 has read s_vals
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      if (kept[r]) {
-        const uint32_t d = ((key[r] - kbase) >> shift) & (R - 1);
-        s_vals[s_wh[wave][d] + rank[r]] = pay[r];
-      }
-    }
+    for (int r = 0; r < kRounds; ++r)
+      if (kept[r]) s_vals[rank[r]] = pay[r];
     __syncthreads();
     for (int i = t; i < count; i += kThreads) {
-      const uint32_t d = ((s_keys[i] - kbase) >> shift) & (R - 1);
-      pl.to[s_gbase[d] + (uint32_t)i] = s_vals[i];
+      const uint32_t k = s_keys[i];
+      const uint32_t dst =
+          keys_out ? s_gbase[((k - kbase) >> shift) & (R - 1)] + (uint32_t)i : k;
+      pl.to[dst] = s_vals[i];
     }
   }
 }
