@@ -5,9 +5,10 @@ scene whose inputs already sit in HBM: gs_project -> gs_bin_sort ->
 gs_raster_grad (colour + dI/dx, dI/dy, d2I/dxdy) -> gs_upscale_hermite.
 The default workload is the 3M-Gaussian scene (SH degree 3) rendered at
 960x540 and upscaled x4 to 3840x2160.  Throughput is high-res output
-megapixels per second with three frames in flight (--inflight), each on a
-stream and a set of buffers of its own; the same frames one at a time give
-the per-frame latency, reported beside it.
+megapixels per second with four frames in flight (--inflight; the process
+gets eight hardware queues, --hw-queues), each on a stream and a set of
+buffers of its own; the same frames one at a time give the per-frame
+latency, reported beside it.
 
 Beside it the script measures, on the same GPU and with the same number of
 frames in flight, the direct full-resolution render (gs_project +
@@ -18,7 +19,8 @@ plain device copy of the same bytes as a reference), both paths from 8 orbit
 cameras, and the FP64 CPU oracle on a bounded sample of the same frame plus,
 on one thread, the whole tiny frame (rank 0, N = 1).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene_x4] [--inflight 3]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene_x4] [--inflight 4]
+                       [--hw-queues 8]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -712,8 +714,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="scene_x4", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", type=int, default=32)
-    ap.add_argument("--inflight", type=int, default=3,
+    ap.add_argument("--inflight", type=int, default=4,
                     help="frames in flight on streams of their own (upscaled and direct paths alike)")
+    ap.add_argument("--hw-queues", type=int, default=8,
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, set before HIP starts); "
+                         "with HIP's default of four, four frames' streams and the default stream "
+                         "share them")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle compositing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-orbit", action="store_true", help="skip the 8 orbit-camera timings")
@@ -727,6 +733,9 @@ def main():
     if args.cpu_tiny_child:
         cpu_tiny_child()
         return
+    if not 1 <= args.hw_queues <= 16:
+        raise SystemExit("--hw-queues must be in [1, 16]")
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)  # read when HIP starts (first GPU use)
     # before anything touches the GPU: the single-thread oracle run is a child process
     tiny_1t = None
     if not args.no_cpu_baseline and WORKLOADS[args.workload][0] not in ("batch", "train"):
