@@ -333,7 +333,7 @@ def test_tile_sizes_agree(torch_mod, oracle):
         assert_within(err, masked, max_masked_frac=1.0)
 
 
-@pytest.mark.parametrize("depth", [2, 3])
+@pytest.mark.parametrize("depth", [2, 3, 4])
 def test_frames_in_flight_match_serial_frames(torch_mod, depth):
     """FramePipeline: frames of different cameras in flight on several
     streams at once give, bit for bit, the frames a lone renderer gives."""
@@ -412,9 +412,9 @@ def test_frames_in_flight_recover_from_pair_overflow(torch_mod):
         np.testing.assert_array_equal(ups[i].cpu().numpy(), up_ref)
 
 
-def test_scene_x4_three_in_flight_equals_serial(torch_mod):
+def test_scene_x4_four_in_flight_equals_serial(torch_mod):
     """The benchmark's launch configuration (3M-Gaussian scene, 960x540 with
-    derivatives, x4 to 3840x2160, 32x32 list tiles, three frames in flight)
+    derivatives, x4 to 3840x2160, 32x32 list tiles, four frames in flight)
     gives, bit for bit, the serial frame at the same list tile, which
     test_e2e_scene_x4_full_size_sampled checks against the oracle."""
     torch = torch_mod
@@ -428,9 +428,10 @@ def test_scene_x4_three_in_flight_equals_serial(torch_mod):
     print("scene x4: serial frame", flush=True)
     up_ref, low_ref = rd.render_upscaled(cam, cfg, W, H)
     up_ref, low_ref = up_ref.cpu().numpy(), low_ref.cpu().numpy()
-    pipe = FramePipeline(rd, 3)
-    lows = [torch.empty((540, 960, 12), dtype=torch.float32, device="cuda") for _ in range(3)]
-    ups = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(3)]
+    depth = 4
+    pipe = FramePipeline(rd, depth)
+    lows = [torch.empty((540, 960, 12), dtype=torch.float32, device="cuda") for _ in range(depth)]
+    ups = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(depth)]
 
     def frame(r):
         i = pipe.slots.index(r)
@@ -440,15 +441,15 @@ def test_scene_x4_three_in_flight_equals_serial(torch_mod):
         r.upscale(lows[i], W, H, ups[i])
 
     for rnd in range(3):
-        print(f"scene x4: three in flight, round {rnd}", flush=True)
-        for _ in range(3):
+        print(f"scene x4: {depth} in flight, round {rnd}", flush=True)
+        for _ in range(depth):
             pipe.submit(frame)
         if pipe.pairs_fit(cam, cfg):
             break
     else:
         pytest.fail("pairs never fitted")
     torch.cuda.synchronize()
-    for i in range(3):
+    for i in range(depth):
         np.testing.assert_array_equal(lows[i].cpu().numpy(), low_ref)
         np.testing.assert_array_equal(ups[i].cpu().numpy(), up_ref)
 
