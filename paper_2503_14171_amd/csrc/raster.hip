@@ -65,11 +65,12 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
   constexpr int QX = TILE / 8;  // quadrants per tile row
   constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
   static_assert(BATCH >= 16 && BATCH <= NT, "one splat per staging thread");
+  static_assert(BATCH * 16 <= 65536, "the hit lists hold 16-bit byte offsets");
   __shared__ float4 s_a[BATCH];  // mean x, mean y (tile-relative), conic a, conic b
   __shared__ float4 s_b[BATCH];  // conic c, log2 sigma, support, red
   __shared__ float4 s_c[BATCH];  // green, blue (16-byte stride: one LDS address for all three)
   __shared__ uint32_t s_mask[NW > 1 ? BATCH : 1];                // quadrants a staged splat can reach
-  __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];  // per-wave hits, batch order
+  __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];  // per-wave hits (16 j), batch order
 
   // a workgroup covers one TILE x TILE part of a (TILE SUB)^2 list tile
   int64_t tile;
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
           const int j = c0 + lane;
           const bool hit = j < cnt && ((s_mask[j] >> wave) & 1u);
           const uint64_t bal = __ballot(hit);
-          if (hit) s_list[wave][nl + __popcll(bal & lt)] = (uint16_t)j;
+          if (hit) s_list[wave][nl + __popcll(bal & lt)] = (uint16_t)(16 * j);  // byte offset
           nl += __popcll(bal);
         }
       }
@@ -156,16 +157,23 @@ __global__ __launch_bounds__(TILE* TILE) void raster_kernel(RasterParams p,
     if (!done) {
       for (int k = 0; k < nl; ++k) {
         {
-          const int j = NW > 1 ? (int)s_list[wave][k] : k;
-          const float4 ga = s_a[j];
-          const float4 gb = s_b[j];
+          // staged record j sits at byte offset 16 j of s_a, s_b and s_c
+          const int off = NW > 1 ? (int)s_list[wave][k] : 16 * k;
+          const int j = off >> 4;
+          const float4 ga = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_a) + off);
+          const float4 gb = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_b) + off);
+          const float4 gc = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_c) + off);
           const float dx = fx - ga.x, dy = fy - ga.y;
           const float u = fmaf(ga.z, dx, ga.w * dy);  // (Q d)_x
           const float v = fmaf(ga.w, dx, gb.x * dy);  // (Q d)_y
           const float q = fmaf(dx, u, dy * v);        // d^T Q d
+          // the colour is read with the other fields: left to itself the
+          // compiler moves its reads into the blend branch, after the exp,
+          // where their latency is not hidden (this empty statement only
+          // consumes the registers)
+          asm volatile("" ::"v"(gc.x), "v"(gc.y), "v"(gb.w));
           if (AUX && !done) ++ne;
           if (!done && q <= gb.z) {                   // alpha >= alpha_min
-            const float4 gc = s_c[j];
             // the exponent is >= log2(alpha_min) > -126: no denormal handling needed
             const float a0 = __builtin_amdgcn_exp2f(fmaf(q, -kHalfLog2e, gb.y));
             // clamped at alpha_max with zero screen derivatives: sa scales them
