@@ -17,9 +17,11 @@
 // output rows; V and D of a low-res row are computed once per lane and reused
 // for every output row of the cell and for the next cell (which shares the
 // row), so a lane reads each low-res row once and spends 12 FMAs per output
-// pixel plus 24 per low-res row.  A wave stores 64 consecutive 12-byte pixels
-// (768 contiguous bytes) per output row, with non-temporal stores (measured
-// 24 us instead of 37 us for 960x540 -> 3840x2160 on MI355X).
+// pixel plus 24 per low-res row; the row's cell index and local coordinate
+// advance incrementally from row to row (no division per row).  A wave
+// stores 64 consecutive 12-byte pixels (768 contiguous bytes) per output row,
+// with non-temporal stores (they keep the output from displacing the input
+// in L2 and the MALL).
 #include "upscale_common.h"
 
 namespace gsup {
@@ -72,11 +74,28 @@ __global__ __launch_bounds__(kThreads) void upscale_kernel(UpParams p,
 
   float V0[3], D0[3], V1[3], D1[3];
   int jcur = -2;
+  // The rows walk the cell index incrementally: the numerator of the row
+  // mapping (axis_map) grows by 2h per output row, so jf and the remainder
+  // rem = num - jf den carry over and j, t come out exactly as axis_map gives
+  // them.  A 64-bit division per row, computed on the scalar unit that the
+  // waves of a CU share, had bounded the kernel.
+  const int64_t den = 2 * (int64_t)H, step = 2 * (int64_t)h;
+  int64_t jf, rem;
+  {
+    const int64_t num = (int64_t)(2 * Y0 + 1) * h - H;
+    jf = floor_div(num, den);
+    rem = num - jf * den;
+  }
   float* o = out + ((int64_t)Y0 * W + X) * 3;
   for (int Y = Y0; Y < Y1; ++Y, o += (int64_t)W * 3) {
-    int j;
-    float ty;
-    axis_map(Y, h, H, j, ty);
+    const int64_t cl = jf < 0 ? 0 : (jf > h - 2 ? h - 2 : jf);  // axis_map's clamp
+    const int j = (int)cl;
+    const float ty = (float)((jf - cl) * den + rem) / (float)den;
+    rem += step;
+    while (rem >= den) {
+      rem -= den;
+      ++jf;
+    }
     if (j != jcur) {
       if (j == jcur + 1) {
 #pragma unroll
