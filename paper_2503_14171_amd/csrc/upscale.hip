@@ -17,8 +17,8 @@
 // output rows; V and D of a low-res row are computed once per lane and reused
 // for every output row of the cell and for the next cell (which shares the
 // row), so a lane reads each low-res row once and spends 12 FMAs per output
-// pixel plus 24 per low-res row; the row's cell index and local coordinate
-// advance incrementally from row to row (no division per row).  A wave
+// pixel plus 24 per low-res row; each row's cell index and Hermite weights
+// are computed once per block (no division per row and lane).  A wave
 // stores 64 consecutive 12-byte pixels (768 contiguous bytes) per output row,
 // with non-temporal stores (they keep the output from displacing the input
 // in L2 and the MALL).
@@ -64,8 +64,26 @@ __global__ __launch_bounds__(kThreads) void upscale_kernel(UpParams p,
   const int bx = (int)(local % strips), by = (int)(local / strips);
   const int X = bx * kThreads + threadIdx.x;
   const int Y0 = by * ROWS;
-  if (X >= W || Y0 >= H) return;
+  if (Y0 >= H) return;  // uniform over the block
   const int Y1 = min(Y0 + ROWS, H);
+  // The band's rows, once per block: each row's cell index and Hermite
+  // weights are the same for every lane, so ROWS threads compute them into
+  // LDS and the row loop reads them.  Computing them per lane and row (a
+  // 64-bit division for the cell index on the scalar unit the CU's waves
+  // share, a float division and the weights on every lane) had bounded the
+  // kernel.
+  __shared__ float4 s_hy[ROWS];
+  __shared__ int s_j[ROWS];
+  if ((int)threadIdx.x < Y1 - Y0) {
+    int j;
+    float ty, a0, a1, a2, a3;
+    axis_map(Y0 + (int)threadIdx.x, h, H, j, ty);
+    hermite(ty, a0, a1, a2, a3);
+    s_hy[threadIdx.x] = make_float4(a0, a1, a2, a3);
+    s_j[threadIdx.x] = j;
+  }
+  __syncthreads();
+  if (X >= W) return;
   int i;
   float tx;
   axis_map(X, w, W, i, tx);
@@ -74,28 +92,9 @@ __global__ __launch_bounds__(kThreads) void upscale_kernel(UpParams p,
 
   float V0[3], D0[3], V1[3], D1[3];
   int jcur = -2;
-  // The rows walk the cell index incrementally: the numerator of the row
-  // mapping (axis_map) grows by 2h per output row, so jf and the remainder
-  // rem = num - jf den carry over and j, t come out exactly as axis_map gives
-  // them.  A 64-bit division per row, computed on the scalar unit that the
-  // waves of a CU share, had bounded the kernel.
-  const int64_t den = 2 * (int64_t)H, step = 2 * (int64_t)h;
-  int64_t jf, rem;
-  {
-    const int64_t num = (int64_t)(2 * Y0 + 1) * h - H;
-    jf = floor_div(num, den);
-    rem = num - jf * den;
-  }
   float* o = out + ((int64_t)Y0 * W + X) * 3;
-  for (int Y = Y0; Y < Y1; ++Y, o += (int64_t)W * 3) {
-    const int64_t cl = jf < 0 ? 0 : (jf > h - 2 ? h - 2 : jf);  // axis_map's clamp
-    const int j = (int)cl;
-    const float ty = (float)((jf - cl) * den + rem) / (float)den;
-    rem += step;
-    while (rem >= den) {
-      rem -= den;
-      ++jf;
-    }
+  for (int r = 0; r < Y1 - Y0; ++r, o += (int64_t)W * 3) {
+    const int j = s_j[r];
     if (j != jcur) {
       if (j == jcur + 1) {
 #pragma unroll
@@ -109,8 +108,8 @@ __global__ __launch_bounds__(kThreads) void upscale_kernel(UpParams p,
       row_terms(in, w, j + 1, i, hx0, hx1, hx2, hx3, V1, D1);
       jcur = j;
     }
-    float hy0, hy1, hy2, hy3;
-    hermite(ty, hy0, hy1, hy2, hy3);
+    const float4 hy = s_hy[r];
+    const float hy0 = hy.x, hy1 = hy.y, hy2 = hy.z, hy3 = hy.w;
     // streaming output: non-temporal stores keep it from displacing the input in L2/MALL
 #pragma unroll
     for (int c = 0; c < 3; ++c)
