@@ -113,6 +113,7 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
   __shared__ int32_t s_id[BATCH];
   __shared__ uint32_t s_mask[NW > 1 ? BATCH : 1];
   __shared__ uint16_t s_list[NW > 1 ? NW : 1][NW > 1 ? BATCH : 1];
+  __shared__ float s_acc[BATCH * 9];  // the batch's splat gradients, summed over the block's waves
   __shared__ int s_end;
 
   // the same workgroup-to-pixel layout as the forward (identical FP32 offsets)
@@ -182,6 +183,8 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
       s_b[t] = make_float4(q.z, opacity_log2(q.w), c.w, c.x);
       s_c[t] = make_float4(c.y, c.z, 1.f / q.w, 0.f);
       s_id[t] = id;
+#pragma unroll
+      for (int f = 0; f < 9; ++f) s_acc[t * 9 + f] = 0.f;
       if (NW > 1) {
         const float det = q.x * q.z - q.y * q.y;
         if (det > 0.f) {
@@ -286,8 +289,14 @@ __global__ __launch_bounds__(TILE* TILE) void raster_bwd_kernel(
       if (__ballot(act) != 0) {
         int comp;
         const float r = wave_reduce9(g, lane, comp);
-        if ((lane & 3) == 0 && comp < 9) atomicAdd(dsplat + (int64_t)s_id[j] * 9 + comp, r);
+        if ((lane & 3) == 0 && comp < 9) atomicAdd(&s_acc[j * 9 + comp], r);
       }
+    }
+    // one global add per (splat, field) the block touched
+    __syncthreads();
+    for (int e = t; e < cnt * 9; e += NT) {
+      const float v = s_acc[e];
+      if (v != 0.f) atomicAdd(dsplat + (int64_t)s_id[e / 9] * 9 + e % 9, v);
     }
   }
 }
